@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the stripe-CZT Fresnel zone plate propagation on one MI355X.
+
+Workload (default): the binary-amplitude FZP of D = 1.0 m, f/5 (f = 5 m),
+lambda = 632.8 nm, sampled on 1048576^2 points (never materialised) and
+propagated onto a 512^2 ROI spanning +-8 lambda f/# at focus.  One step is one
+full propagation of that aperture (row pass, column pass, output factor) plus
+the focal-spot metrics (FWHM, DE, MTF), i.e. every step of the hot path.
+
+Metric: aperture Gsamples/s into the ROI (N^2 per step / step time) for the
+split-BF16 MFMA path, next to the float64 Bluestein path on the same GPU; the
+split result is valid only when its ROI intensity is within rel-L2 1e-4 of the
+float64 path's.  Inputs are synthetic and analytic (the zone plate itself).
+
+Prints exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fzp1m", choices=["fzp2mm", "fzp20mm", "fzp1m"])
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the float64 comparison path")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=96, help="aperture rows in the CPU oracle sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# MI355X published peaks
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(w, rows_n: int):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload:
+    `rows_n` aperture rows through the middle of the aperture, Bluestein form."""
+    import numpy as np
+    from oracle import fzp_oracle as O
+    a = O.Aperture(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    i = O.Instance(lam=w["lambda0"], M=w["M"])
+    N = a.N
+    j0 = N // 2 - rows_n // 2
+    t = time.perf_counter()
+    O.propagate(a, i, method="bluestein", rows=(j0, j0 + rows_n), stripe=32)
+    dt = time.perf_counter() - t
+    return dict(value=rows_n * N / dt / 1e9, unit="Gsamples/s", cores=1, kind="oracle",
+                sample=f"{rows_n} aperture rows x {N} columns through the centre of the {w['D']} m aperture "
+                       f"(float64 Bluestein form, scipy.fft single worker), {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
+              "(the stripe-range call fzp_propagate_roi_range is the one-GPU share).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2609_01978_amd as P
+    from fzp_inputs import workload
+
+    w = workload(args.workload)
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    N, M, S = w["N"], w["M"], w["stripe"]
+    samples = float(N) * float(N)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def run_path(path, steps, warmup):
+        plan = P.Plan(ap, [inst], path=path, stripe_rows=S)
+        ws, roi = plan.alloc(dev)
+        t0 = time.perf_counter()
+        plan.prepare(ws)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        for k in range(warmup):
+            plan.propagate(ws, roi)
+            plan.metrics(ws, roi)
+            log(f"{path} warmup {k + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        plan.profile(True)
+        plan.profile_read(reset=True)
+        t0 = time.perf_counter()
+        metrics = None
+        for k in range(steps):
+            plan.propagate(ws, roi)
+            metrics = plan.metrics(ws, roi)[0]   # synchronises the stream
+            log(f"{path} step {k + 1}/{steps} done")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = plan.profile_read(reset=True)
+        plan.profile(False)
+        I = plan.roi_view(roi, 0).abs().square().cpu().numpy()
+        info = plan.info()
+        del ws, roi
+        torch.cuda.empty_cache()
+        return dict(ms=dt / steps * 1e3, prep_s=t_prep, prof=prof, metrics=metrics, I=I, info=info)
+
+    log(f"workload {args.workload}: N={N} M={M} stripe={S}")
+    split = run_path("split", args.steps, args.warmup)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_path("fp64", args.fp64_steps, 0)
+
+    value = samples / (split["ms"] * 1e-3) / 1e9
+    rel = None
+    if fp64 is not None:
+        rel = float(np.linalg.norm(split["I"] - fp64["I"]) / np.linalg.norm(fp64["I"]))
+
+    # roofline of the dominant kernel (split row pass): algorithmic flops per launch =
+    # 16 M flops per aperture sample (binary stripe, hi/lo operand: two real products of
+    # 2 real columns per complex ROI column) x the samples of the launch's rows.
+    pr = split["prof"]
+    row_launch_ms = pr["row_ms"] / max(pr["row_launches"], 1)
+    launches_per_step = pr["row_launches"] / max(args.steps, 1)
+    samples_per_launch = samples / max(launches_per_step, 1)
+    flops_per_launch = 16.0 * M * samples_per_launch
+    achieved = flops_per_launch / (row_launch_ms * 1e-3) / 1e12
+    roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
+                    kernel="k_row_pass_split", launch_ms=round(row_launch_ms, 3),
+                    launches_per_step=launches_per_step)
+
+    out = {
+        "metric": "aperture Gsamples/s into ROI: split-BF16 MFMA vs FP64 Bluestein, rel-L2<=1e-4",
+        "value": round(value, 3),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(split["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"binary FZP D={w['D']} m f/5 lambda=632.8 nm, N={N}^2 samples, ROI {M}^2, "
+                               f"stripe {S} rows", "N": N, "M": M, "stripe_rows": S,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "split_bf16": {"gsamples_s": round(value, 3), "ms_per_step": round(split["ms"], 3),
+                       "row_pass_ms": round(pr["row_ms"] / max(args.steps, 1), 3),
+                       "col_pass_ms": round(pr["col_ms"] / max(args.steps, 1), 3),
+                       "prepare_s": round(split["prep_s"], 3), "metrics": split["metrics"]},
+        "valid_rel_l2_le_1e-4": (rel is not None and rel <= 1e-4),
+        "rel_l2_split_vs_fp64": rel,
+    }
+    if fp64 is not None:
+        pf = fp64["prof"]
+        out["fp64_bluestein"] = {"gsamples_s": round(samples / (fp64["ms"] * 1e-3) / 1e9, 3),
+                                 "ms_per_step": round(fp64["ms"], 3),
+                                 "row_pass_ms": round(pf["row_ms"] / max(args.fp64_steps, 1), 3),
+                                 "col_pass_ms": round(pf["col_ms"] / max(args.fp64_steps, 1), 3),
+                                 "prepare_s": round(fp64["prep_s"], 3), "metrics": fp64["metrics"],
+                                 "fft_len": fp64["info"]["fft_len"], "block": fp64["info"]["block"]}
+        out["speedup_split_vs_fp64"] = round(fp64["ms"] / split["ms"], 3)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

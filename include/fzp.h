@@ -1,0 +1,187 @@
+/*
+ * fzp.h - C ABI of the MI355X stripe-CZT Fresnel zone plate propagator.
+ *
+ * The library evaluates the focal-plane field of a full, unscaled, 2-D
+ * binary-amplitude Fresnel zone plate (FZP) on a fixed region of interest
+ * (ROI), by the separable chirp-z transform of the paper's CZT method
+ * (Sec. 2.6, Eqs. 9-10; Sec. 3.3, Fig. 2; revised GPU engine, Sec. 6, Fig. 18):
+ *
+ *   U(x'_q, y'_p) = e^{ikz}/(i lambda z) e^{i pi (x'_q^2 + y'_p^2)/(lambda z)} dx^2
+ *                   sum_{j,i} t_ji e^{i phi_ji} e^{i pi (x_i^2 + y_j^2)/(lambda z)}
+ *                             e^{-2 pi i (x_i x'_q + y_j y'_p)/(lambda z)}        (Eq. 2)
+ *
+ * with x_i = (i - (N-1)/2) dx, x'_q = x0 + (q - M/2) dx_out, dx_out = 2 hw / M,
+ * and the binary zone mask t_ji of Sec. 2.2 (paraxial radii r_n^2 = n lambda0 f0,
+ * Eq. 4): with the exact integer K = (2i-N+1)^2 + (2j-N+1)^2 = 4 r^2/dx^2 and the
+ * float64 constant kappa = dx*dx / (4*lambda0*f0), a sample is open iff
+ * K <= K_max (inside the aperture disc; K_max = N^2 for the default pitch D/N,
+ * floor((D/pitch)^2) otherwise) and floor(K*kappa) is odd (even when
+ * centre_open is set).  phi = 2 pi h / lambda is an optional phase screen of
+ * straight Gaussian creases, h = sum_k H_k exp(-d_k^2/(2 sigma_k^2)),
+ * d_k = x cos(theta_k) + y sin(theta_k) - rho_k, sigma_k = width_k/(2 sqrt(2 ln 2)).
+ * The N x N aperture is never stored: every stripe of rows is generated on the
+ * device from these formulas.
+ *
+ * Conventions
+ *  - Lengths in metres, angles in radians.
+ *  - Complex buffers are interleaved (re, im) float64.  The ROI of instance k is
+ *    row-major [y = p][x = q], M_k x M_k complex, starting at complex element
+ *    fzp_roi_offset(plan, k) of the caller's ROI buffer.
+ *  - Device buffers (workspace, ROI) are owned by the caller (allocated through
+ *    PyTorch in the Python binding).  A plan owns host memory only; its device
+ *    tables live in the caller's workspace.
+ *  - All device work is enqueued on the caller's HIP stream (hipStream_t passed
+ *    as void*; NULL is the null stream).  A plan may be used by one stream at a
+ *    time.  fzp_metrics synchronises the stream before it returns.
+ *  - Every call returns a status and never aborts; no C++ exception crosses the
+ *    ABI.  fzp_last_error() gives a thread-local message for the last non-OK
+ *    status.  A device fault surfaces as FZP_E_DEVICE on the next call that
+ *    synchronises.
+ *  - Determinism: no float atomics anywhere; both paths are bit-reproducible
+ *    run to run for the same plan options.
+ */
+#ifndef FZP_H
+#define FZP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fzp_plan_s *fzp_plan_t;
+
+typedef int32_t fzp_status_t;
+#define FZP_OK 0
+#define FZP_E_INVAL (-1)       /* an argument is out of range, not finite or NULL */
+#define FZP_E_SAMPLING (-2)    /* pitch coarser than the Nyquist limit of Eq. 6 */
+#define FZP_E_NOMEM (-3)       /* workspace larger than the caller's limit */
+#define FZP_E_DEVICE (-4)      /* a HIP call failed */
+#define FZP_E_UNSUPPORTED (-5) /* valid but outside what this build handles */
+
+/* Row-pass evaluation path. */
+#define FZP_PATH_FP64_BLUESTEIN 0 /* Bluestein CZT per row, float64 throughout (Sec. 2.6) */
+#define FZP_PATH_SPLIT_BF16 1     /* row pass as a BF16 MFMA complex GEMM with hi/lo split
+                                     operands and float32 accumulation; column pass and
+                                     the ROI sum in float64 */
+
+/* Plan flags. */
+#define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */
+
+typedef struct {
+  double D;          /* aperture diameter */
+  double f0;         /* design focal length */
+  double lambda0;    /* design wavelength (zone radii r_n^2 = n lambda0 f0) */
+  double pitch;      /* sample pitch; 0 means D / N */
+  int64_t N;         /* samples per side, 1 .. 2^21 */
+  int32_t centre_open; /* 0: central zone opaque (odd zones open); 1: central zone open */
+  int32_t reserved;
+} fzp_aperture_t;
+
+typedef struct {
+  double theta;  /* ridge direction normal angle */
+  double offset; /* signed distance of the ridge line from the axis */
+  double width;  /* ridge FWHM */
+  double height; /* ridge optical path difference */
+} fzp_crease_t;
+
+typedef struct {
+  double lambda;     /* wavelength */
+  double z;          /* propagation distance; 0 means the first-order focus f0*lambda0/lambda */
+  double x0, y0;     /* ROI centre */
+  double half_width; /* ROI half width; 0 means 8*lambda*z/D */
+  int32_t M;         /* ROI samples per side, 2 .. 2048 */
+  int32_t n_creases; /* 0 .. 64 */
+  const fzp_crease_t *creases; /* host array of n_creases, copied by fzp_plan */
+} fzp_instance_t;
+
+typedef struct {
+  int32_t path;         /* FZP_PATH_* */
+  int32_t stripe_rows;  /* rows per stripe, the row-pass work unit; 0 = path default */
+  int64_t chunk_rows;   /* rows transformed between two column passes; 0 = automatic */
+  uint64_t workspace_limit; /* bytes; 0 = no limit.  fzp_plan fails with FZP_E_NOMEM
+                               if the workspace would exceed it */
+  int32_t flags;        /* FZP_FLAG_* */
+  int32_t reserved;
+} fzp_options_t;
+
+/* Main-lobe metrics of one instance (shared metric extractor, Sec. 3.3 stage 4
+ * and Fig. 18 stage 5).  fwhm_* come from a not-a-knot cubic spline through the
+ * ROI row (column) holding the brightest sample; de is the power inside
+ * r_null = j_{1,1}/pi * lambda z / D around the ROI centre over
+ * p_in = (#samples in the disc) dx^2; mtf_half_cut is the radially averaged
+ * |FFT2(I)|/|FFT2(I)|(0) at nu_cut/2, nu_cut = D/(lambda z); strehl is
+ * i_peak / (pi R^2/(lambda z))^2. */
+typedef struct {
+  double fwhm_x, fwhm_y, de, mtf_half_cut, strehl, i_peak, p_in, p_lobe;
+} fzp_metrics_t;
+
+/* Validate the aperture, the n_inst instances and the options, and build a plan
+ * (grids, CZT parameters of Eq. 10, workspace layout).  Host only; no device
+ * call.  Errors: FZP_E_INVAL (NULL or out-of-range argument), FZP_E_SAMPLING
+ * (pitch > lambda0 f0 / (2 D), Eq. 6, unless FZP_FLAG_ALLOW_UNDERSAMPLED),
+ * FZP_E_NOMEM (workspace over options->workspace_limit), FZP_E_UNSUPPORTED. */
+fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t *inst, int32_t n_inst,
+                      const fzp_options_t *opt, fzp_plan_t *out);
+
+/* Bytes of device workspace the plan needs (tables + stripe buffers + metric
+ * scratch).  The caller allocates it (256-byte aligned). */
+fzp_status_t fzp_plan_workspace_size(fzp_plan_t p, size_t *bytes);
+
+/* Total ROI buffer length in complex elements (sum over instances of M^2), and
+ * the offset of instance k inside it. */
+fzp_status_t fzp_roi_elements(fzp_plan_t p, int64_t *n_complex);
+fzp_status_t fzp_roi_offset(fzp_plan_t p, int32_t k, int64_t *offset_complex);
+
+/* Build the plan's device tables (Bluestein chirps and filter spectra, the
+ * split-path operand tables) inside `workspace`.  Asynchronous on `stream`.
+ * fzp_propagate_roi calls it itself when given a workspace it has not seen. */
+fzp_status_t fzp_prepare(fzp_plan_t p, void *workspace, void *stream);
+
+/* Propagate every instance of the plan: roi_dev receives U (Eq. 2) for all
+ * aperture rows.  Asynchronous on `stream`. */
+fzp_status_t fzp_propagate_roi(fzp_plan_t p, void *workspace, double *roi_dev, void *stream);
+
+/* Contribution of aperture rows row_begin .. row_end-1 only (0 <= begin <= end
+ * <= N).  With accumulate = 0 the ROI is overwritten, otherwise added to.  The
+ * contributions of a partition of [0, N) into ranges that start on multiples of
+ * the plan's chunk_rows add up bit-for-bit to fzp_propagate_roi (resume after
+ * interruption; one GPU's share of a multi-GPU run). */
+fzp_status_t fzp_propagate_roi_range(fzp_plan_t p, void *workspace, double *roi_dev,
+                                     int64_t row_begin, int64_t row_end, int32_t accumulate,
+                                     void *stream);
+
+/* Metrics of every instance from roi_dev (as written by fzp_propagate_roi),
+ * computed on the device; out_host receives n_inst records.  Synchronises
+ * `stream`.  Instances with M not a power of two in 8 .. 4096 get NaN MTF. */
+fzp_status_t fzp_metrics(fzp_plan_t p, void *workspace, const double *roi_dev,
+                         fzp_metrics_t *out_host, void *stream);
+
+/* Plan facts for reporting: FFT length L, Bluestein block B, rows per chunk,
+ * stripe rows, path, samples in the aperture disc, and the float64 zone
+ * constant kappa.  Any pointer may be NULL. */
+fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64_t *chunk_rows,
+                           int32_t *stripe_rows, int32_t *path, int64_t *disc_samples,
+                           double *kappa);
+
+/* Kernel timing.  While enabled, every row-pass and column-pass launch of
+ * fzp_propagate_roi(_range) is bracketed by HIP events recorded on the
+ * caller's stream, so each interval covers exactly that kernel.
+ * fzp_profile_read waits for the recorded events and returns the accumulated
+ * milliseconds and launch counts since the last reset (reset != 0 clears them).
+ * Any output pointer may be NULL. */
+fzp_status_t fzp_profile_enable(fzp_plan_t p, int32_t on);
+fzp_status_t fzp_profile_read(fzp_plan_t p, double *row_ms, int64_t *row_launches, double *col_ms,
+                              int64_t *col_launches, int32_t reset);
+
+void fzp_destroy(fzp_plan_t p);
+
+/* Thread-local message of the last non-OK status on this thread. */
+const char *fzp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FZP_H */

@@ -1,0 +1,250 @@
+"""ctypes binding of ``libfzp.so`` (the C ABI declared in ``include/fzp.h``).
+
+Argument marshalling only: every step of the propagation and of the metric
+extraction runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current HIP stream.  The library must be built
+(``python -m paper_2609_01978_amd.build``); importing this module fails loudly
+when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfzp.so")
+
+FZP_OK = 0
+FZP_E_INVAL = -1
+FZP_E_SAMPLING = -2
+FZP_E_NOMEM = -3
+FZP_E_DEVICE = -4
+FZP_E_UNSUPPORTED = -5
+STATUS_NAMES = {0: "FZP_OK", -1: "FZP_E_INVAL", -2: "FZP_E_SAMPLING", -3: "FZP_E_NOMEM",
+                -4: "FZP_E_DEVICE", -5: "FZP_E_UNSUPPORTED"}
+
+PATH_FP64_BLUESTEIN = 0
+PATH_SPLIT_BF16 = 1
+FLAG_ALLOW_UNDERSAMPLED = 1
+
+EXPORTED = [
+    "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
+    "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
+    "fzp_last_error", "fzp_profile_enable", "fzp_profile_read",
+]
+
+
+class FZPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Aperture(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("f0", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("pitch", ctypes.c_double), ("N", ctypes.c_int64), ("centre_open", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Crease(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("offset", ctypes.c_double), ("width", ctypes.c_double),
+                ("height", ctypes.c_double)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("z", ctypes.c_double), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("half_width", ctypes.c_double), ("M", ctypes.c_int32),
+                ("n_creases", ctypes.c_int32), ("creases", ctypes.POINTER(Crease))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("stripe_rows", ctypes.c_int32), ("chunk_rows", ctypes.c_int64),
+                ("workspace_limit", ctypes.c_uint64), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Metrics(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("fwhm_x", "fwhm_y", "de", "mtf_half_cut", "strehl", "i_peak", "p_in", "p_lobe")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libfzp.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_01978_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int32
+    P = ctypes.c_void_p
+    lib.fzp_plan.argtypes = [ctypes.POINTER(Aperture), ctypes.POINTER(Instance), ctypes.c_int32,
+                             ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.fzp_plan.restype = st
+    lib.fzp_plan_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fzp_plan_workspace_size.restype = st
+    lib.fzp_roi_elements.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.fzp_roi_elements.restype = st
+    lib.fzp_roi_offset.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.fzp_roi_offset.restype = st
+    lib.fzp_prepare.argtypes = [P, P, P]
+    lib.fzp_prepare.restype = st
+    lib.fzp_propagate_roi.argtypes = [P, P, P, P]
+    lib.fzp_propagate_roi.restype = st
+    lib.fzp_propagate_roi_range.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
+    lib.fzp_propagate_roi_range.restype = st
+    lib.fzp_metrics.argtypes = [P, P, P, ctypes.POINTER(Metrics), P]
+    lib.fzp_metrics.restype = st
+    lib.fzp_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double)]
+    lib.fzp_plan_info.restype = st
+    lib.fzp_profile_enable.argtypes = [P, ctypes.c_int32]
+    lib.fzp_profile_enable.restype = st
+    lib.fzp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.fzp_profile_read.restype = st
+    lib.fzp_destroy.argtypes = [P]
+    lib.fzp_destroy.restype = None
+    lib.fzp_last_error.argtypes = []
+    lib.fzp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(lib, status: int):
+    if status != FZP_OK:
+        raise FZPError(status, lib.fzp_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+class Plan:
+    """A propagation plan: an aperture and one or more instances (lambda, z, ROI, creases)."""
+
+    def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
+                 chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False):
+        lib = load_library()
+        self._lib = lib
+        ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
+                      pitch=aperture.get("pitch", 0.0), N=int(aperture["N"]),
+                      centre_open=int(aperture.get("centre_open", 0)), reserved=0)
+        n = len(instances)
+        arr = (Instance * n)()
+        self._crease_bufs = []
+        for k, inst in enumerate(instances):
+            cr = inst.get("creases")
+            ncr = 0 if cr is None else len(cr)
+            cbuf = (Crease * max(ncr, 1))()
+            for c in range(ncr):
+                cbuf[c] = Crease(*[float(v) for v in cr[c]])
+            self._crease_bufs.append(cbuf)
+            arr[k] = Instance(lambda_=inst["lam"], z=inst.get("z", 0.0), x0=inst.get("x0", 0.0),
+                              y0=inst.get("y0", 0.0), half_width=inst.get("half_width", 0.0), M=int(inst["M"]),
+                              n_creases=ncr, creases=ctypes.cast(cbuf, ctypes.POINTER(Crease)))
+        p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16}[path] if isinstance(path, str) else int(path)
+        opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
+                      flags=FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0, reserved=0)
+        h = ctypes.c_void_p()
+        _check(lib, lib.fzp_plan(ctypes.byref(ap), arr, n, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.n_instances = n
+        self.Ms = [int(inst["M"]) for inst in instances]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fzp_destroy(h)
+            self._h = None
+
+    # -- sizes ---------------------------------------------------------------
+    @property
+    def workspace_size(self) -> int:
+        v = ctypes.c_size_t()
+        _check(self._lib, self._lib.fzp_plan_workspace_size(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    @property
+    def roi_elements(self) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib, self._lib.fzp_roi_elements(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def roi_offset(self, k: int) -> int:
+        v = ctypes.c_int64()
+        _check(self._lib, self._lib.fzp_roi_offset(self._h, k, ctypes.byref(v)))
+        return int(v.value)
+
+    def info(self) -> dict:
+        a, b, s, pth = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        c, ds = ctypes.c_int64(), ctypes.c_int64()
+        kap = ctypes.c_double()
+        _check(self._lib, self._lib.fzp_plan_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                  ctypes.byref(s), ctypes.byref(pth), ctypes.byref(ds),
+                                                  ctypes.byref(kap)))
+        return dict(fft_len=a.value, block=b.value, chunk_rows=c.value, stripe_rows=s.value, path=pth.value,
+                    disc_samples=ds.value, kappa=kap.value)
+
+    # -- device buffers (torch) ---------------------------------------------
+    def alloc(self, device="cuda"):
+        """(workspace, roi): a uint8 workspace and a float64 ROI buffer of 2 * roi_elements."""
+        import torch
+        ws = torch.empty(self.workspace_size, dtype=torch.uint8, device=device)
+        roi = torch.empty(2 * self.roi_elements, dtype=torch.float64, device=device)
+        return ws, roi
+
+    def roi_view(self, roi, k: int):
+        """Complex [M, M] view of instance k inside the ROI buffer."""
+        import torch
+        M = self.Ms[k]
+        off = self.roi_offset(k)
+        return torch.view_as_complex(roi[2 * off: 2 * (off + M * M)].view(M * M, 2)).view(M, M)
+
+    # -- calls ---------------------------------------------------------------
+    def prepare(self, ws, stream=None):
+        _check(self._lib, self._lib.fzp_prepare(self._h, _ptr(ws), _stream_handle(stream)))
+
+    def propagate(self, ws, roi, stream=None):
+        _check(self._lib, self._lib.fzp_propagate_roi(self._h, _ptr(ws), _ptr(roi), _stream_handle(stream)))
+
+    def propagate_range(self, ws, roi, row_begin: int, row_end: int, accumulate: bool = False, stream=None):
+        _check(self._lib, self._lib.fzp_propagate_roi_range(self._h, _ptr(ws), _ptr(roi), int(row_begin),
+                                                            int(row_end), int(bool(accumulate)),
+                                                            _stream_handle(stream)))
+
+    def profile(self, on: bool = True):
+        """Bracket every row-pass and column-pass launch with HIP events."""
+        _check(self._lib, self._lib.fzp_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """Accumulated kernel milliseconds and launch counts (waits for the events)."""
+        rm, cm = ctypes.c_double(), ctypes.c_double()
+        rn, cn = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib, self._lib.fzp_profile_read(self._h, ctypes.byref(rm), ctypes.byref(rn), ctypes.byref(cm),
+                                                     ctypes.byref(cn), int(bool(reset))))
+        return dict(row_ms=rm.value, row_launches=rn.value, col_ms=cm.value, col_launches=cn.value)
+
+    def metrics(self, ws, roi, stream=None) -> list:
+        out = (Metrics * self.n_instances)()
+        _check(self._lib, self._lib.fzp_metrics(self._h, _ptr(ws), _ptr(roi), out, _stream_handle(stream)))
+        return [out[k].as_dict() for k in range(self.n_instances)]

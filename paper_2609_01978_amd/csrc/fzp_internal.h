@@ -1,0 +1,108 @@
+// Internal structures shared by the host plan (fzp_plan.cpp) and the kernel
+// launchers (*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "fzp.h"
+
+namespace fzp {
+
+constexpr int kFftLen = 4096;     // Bluestein block FFT length (LDS resident)
+constexpr int kFftThreads = 256;  // threads per FFT work-group
+constexpr int kMaxCreases = 64;
+constexpr int kMaxM = 2048;
+
+// Per-crease constants, precomputed on the host in float64:
+// h_k(x,y) = H_k exp(-(x cos + y sin - rho)^2 * inv2s2)
+struct CreaseDev {
+  double c, s, rho, inv2s2, h_over_lambda;  // height / lambda (turns)
+  double pad[3];
+};
+
+// Everything a kernel needs to know about one instance.
+struct InstDev {
+  // aperture
+  int64_t N;
+  double kappa;     // dx*dx / (4 lambda0 f0)
+  double kmax;      // K_max, exact integer in float64
+  int32_t centre_open;
+  int32_t M;
+  int32_t B;        // Bluestein block length (kFftLen - M + 1)
+  int32_t n_creases;
+  double dx;
+  // CZT (Eq. 10) in turns: phase(i, q) = beta c_i^2 / 2 - alpha c_i d_q,
+  // c_i = i - (N-1)/2, d_q = q - M/2 + s
+  double alpha, beta;
+  double sx, sy;
+  // output factor e^{ikz}/(i lambda z) dx^2 e^{i pi (x'^2+y'^2)/(lambda z)}
+  double kz_turns;  // frac(z / lambda) - 1/4
+  double scale;     // dx^2 / (lambda z)
+  double x0, y0, dx_out, inv2lz;  // inv2lz = 1 / (2 lambda z)
+  // metrics: r_null^2, (R^2/(lambda z))^2, MTF read point in radial bins
+  double rnull2, R2_over_lz2, t_mtf;
+  // device tables (pointers into the workspace)
+  const double2 *Hx, *Hy;  // FFT_L(h) / L, h[k] = e^{i pi alpha (k - M/2 + s)^2}
+  const double2 *Dt;       // e^{i pi (beta - alpha) n^2}, n < L
+  const double2 *Qx, *Qy;  // e^{-i pi alpha d^2}
+  const CreaseDev *cr;
+  const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
+  int64_t Npad;
+};
+
+struct InstHost {
+  fzp_instance_t in;  // creases pointer cleared
+  std::vector<fzp_crease_t> creases;
+  double lam, z, hw, dx_out;
+  InstDev dev;
+  size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A;
+  int64_t roi_off;     // complex elements
+  int32_t table_owner; // instance whose split table this one shares (itself if none)
+};
+
+struct Plan {
+  fzp_aperture_t ap;
+  fzp_options_t opt;
+  double dx;
+  double kappa;
+  int64_t kmax;
+  int64_t disc_samples;
+  int32_t S;
+  int64_t chunk_rows;
+  int32_t Mmax;
+  std::vector<InstHost> inst;
+  int64_t roi_elems;
+  size_t off_T, T_bytes;
+  size_t off_scratch, scratch_bytes;
+  size_t ws_bytes;
+  const void *prepared_ws = nullptr;
+  // kernel timing (fzp_profile_*)
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<size_t, int>> ev_marks;  // (first event index, 0 = row / 1 = column)
+  double row_ms = 0.0, col_ms = 0.0;
+  int64_t row_n = 0, col_n = 0;
+  ~Plan();
+};
+
+// ---- launchers (fzp_fft.hip, fzp_gemm.hip, fzp_metrics.hip) ----
+hipError_t launch_build_tables(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
+hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
+hipError_t launch_zero(double *buf, int64_t n_doubles, hipStream_t st);
+hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row_end, double2 *T,
+                                hipStream_t st);
+hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
+                                 float2 *T, hipStream_t st);
+hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,
+                           bool t_is_fp32, double2 *roi, hipStream_t st);
+hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,
+                          fzp_metrics_t *dev_out, hipStream_t st);
+size_t metrics_scratch_bytes(int32_t M);
+
+}  // namespace fzp

@@ -1,0 +1,509 @@
+// Host side of the C ABI: argument validation, the grids and chirp-z
+// parameters of each instance (Sec. 3.3 stage 1, Eq. 10; Fig. 18 stage 1),
+// the workspace layout and the stripe/chunk schedule of a propagation.
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <new>
+#include <string>
+
+#include "fzp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fzp_status_t fail(fzp_status_t s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int64_t isqrt64(int64_t v) {
+  if (v <= 0) return 0;
+  int64_t m = (int64_t)std::sqrt((double)v);
+  while (m > 0 && m * m > v) --m;
+  while ((m + 1) * (m + 1) <= v) ++m;
+  return m;
+}
+
+// Samples with K = (2i-N+1)^2 + (2j-N+1)^2 <= kmax (exact integers).
+int64_t disc_count(int64_t N, int64_t kmax) {
+  int64_t total = 0;
+  for (int64_t j = 0; j < N; ++j) {
+    const int64_t cj = 2 * j - N + 1;
+    const int64_t rem = kmax - cj * cj;
+    if (rem < 0) continue;
+    int64_t m = isqrt64(rem);
+    if (m > N - 1) m = N - 1;
+    // c = 2i - N + 1 runs over integers of the parity of N - 1
+    if ((N - 1) % 2 == 0)
+      total += 2 * (m / 2) + 1;
+    else
+      total += 2 * ((m + 1) / 2);
+  }
+  return total;
+}
+
+}  // namespace
+
+struct fzp_plan_s {
+  fzp::Plan plan;
+};
+
+fzp::Plan::~Plan() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+namespace {
+
+// Two events from the plan's pool (created on first use).
+hipError_t take_events(fzp::Plan &p, hipEvent_t &a, hipEvent_t &b, size_t &first) {
+  while (p.ev_pool.size() < p.ev_used + 2) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    p.ev_pool.push_back(e);
+  }
+  first = p.ev_used;
+  a = p.ev_pool[p.ev_used];
+  b = p.ev_pool[p.ev_used + 1];
+  p.ev_used += 2;
+  return hipSuccess;
+}
+
+}  // namespace
+
+using fzp::InstDev;
+using fzp::InstHost;
+using fzp::Plan;
+
+extern "C" const char *fzp_last_error(void) { return g_err.c_str(); }
+
+extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t *inst, int32_t n_inst,
+                                 const fzp_options_t *opt, fzp_plan_t *out) {
+  try {
+    if (!ap || !inst || !out || n_inst <= 0) return fail(FZP_E_INVAL, "fzp_plan: NULL argument or n_inst <= 0");
+    *out = nullptr;
+    fzp_options_t o{};
+    if (opt) o = *opt;
+    if (o.path != FZP_PATH_FP64_BLUESTEIN && o.path != FZP_PATH_SPLIT_BF16)
+      return fail(FZP_E_INVAL, "fzp_plan: unknown path");
+    if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
+      return fail(FZP_E_INVAL, "fzp_plan: D, f0 and lambda0 must be finite and positive");
+    if (!(std::isfinite(ap->pitch) && ap->pitch >= 0.0)) return fail(FZP_E_INVAL, "fzp_plan: pitch must be >= 0");
+    if (ap->N < 1 || ap->N > (int64_t(1) << 21)) return fail(FZP_E_INVAL, "fzp_plan: N must be in 1 .. 2^21");
+    if (ap->centre_open != 0 && ap->centre_open != 1) return fail(FZP_E_INVAL, "fzp_plan: centre_open must be 0 or 1");
+    if (o.stripe_rows < 0 || o.chunk_rows < 0) return fail(FZP_E_INVAL, "fzp_plan: negative stripe or chunk rows");
+
+    auto h = new (std::nothrow) fzp_plan_s;
+    if (!h) return fail(FZP_E_NOMEM, "fzp_plan: out of host memory");
+    Plan &p = h->plan;
+    p.ap = *ap;
+    p.opt = o;
+    const int64_t N = ap->N;
+    p.dx = ap->pitch > 0.0 ? ap->pitch : ap->D / (double)N;
+    // the zone constant, one float64 expression: 4 r^2 / dx^2 = K  =>  r^2/(lambda0 f0) = K * kappa
+    p.kappa = p.dx * p.dx / (4.0 * ap->lambda0 * ap->f0);
+    if (ap->pitch > 0.0) {
+      const double kk = std::floor(std::pow(ap->D / ap->pitch, 2.0));
+      if (!(kk < 9.0e15)) {
+        delete h;
+        return fail(FZP_E_INVAL, "fzp_plan: D / pitch too large");
+      }
+      p.kmax = (int64_t)kk;
+    } else {
+      p.kmax = N * N;
+    }
+    // Eq. 6: dx <= lambda0 f0 / (2 D)
+    if (!(o.flags & FZP_FLAG_ALLOW_UNDERSAMPLED) && p.dx > ap->lambda0 * ap->f0 / (2.0 * ap->D)) {
+      delete h;
+      return fail(FZP_E_SAMPLING, "fzp_plan: pitch exceeds the Nyquist limit lambda0 f0 / (2 D) of Eq. 6");
+    }
+    // zone indices must fit int32 over the whole square grid
+    const double kcorner = 2.0 * (double)(N - 1) * (double)(N - 1);
+    if (!(kcorner * p.kappa < 2.0e9)) {
+      delete h;
+      return fail(FZP_E_UNSUPPORTED, "fzp_plan: zone count beyond 2e9");
+    }
+    p.disc_samples = disc_count(N, p.kmax);
+
+    p.inst.resize(n_inst);
+    p.Mmax = 0;
+    int64_t roi = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      const fzp_instance_t &in = inst[k];
+      InstHost &ih = p.inst[k];
+      if (!finite_pos(in.lambda) || !(std::isfinite(in.z) && in.z >= 0.0) || !std::isfinite(in.x0) ||
+          !std::isfinite(in.y0) || !(std::isfinite(in.half_width) && in.half_width >= 0.0)) {
+        delete h;
+        return fail(FZP_E_INVAL, "fzp_plan: instance " + std::to_string(k) + " has a bad lambda/z/x0/y0/half_width");
+      }
+      if (in.M < 2 || in.M > fzp::kMaxM) {
+        delete h;
+        return fail(FZP_E_INVAL, "fzp_plan: M must be in 2 .. 2048");
+      }
+      if (in.n_creases < 0 || in.n_creases > fzp::kMaxCreases || (in.n_creases > 0 && !in.creases)) {
+        delete h;
+        return fail(FZP_E_INVAL, "fzp_plan: n_creases must be in 0 .. 64 with a crease array");
+      }
+      ih.in = in;
+      ih.in.creases = nullptr;
+      ih.creases.assign(in.creases, in.creases + in.n_creases);
+      for (const auto &c : ih.creases)
+        if (!std::isfinite(c.theta) || !std::isfinite(c.offset) || !finite_pos(c.width) || !std::isfinite(c.height)) {
+          delete h;
+          return fail(FZP_E_INVAL, "fzp_plan: crease parameters must be finite with width > 0");
+        }
+      ih.lam = in.lambda;
+      ih.z = in.z > 0.0 ? in.z : ap->f0 * ap->lambda0 / in.lambda;
+      const double lz = ih.lam * ih.z;
+      ih.hw = in.half_width > 0.0 ? in.half_width : 8.0 * ih.lam * ih.z / ap->D;
+      ih.dx_out = 2.0 * ih.hw / (double)in.M;
+      InstDev &d = ih.dev;
+      std::memset(&d, 0, sizeof(d));
+      d.N = N;
+      d.kappa = p.kappa;
+      d.kmax = (double)p.kmax;
+      d.centre_open = ap->centre_open;
+      d.M = in.M;
+      d.B = fzp::kFftLen - in.M + 1;
+      d.n_creases = in.n_creases;
+      d.dx = p.dx;
+      d.alpha = p.dx * ih.dx_out / lz;
+      d.beta = p.dx * p.dx / lz;
+      d.sx = in.x0 / ih.dx_out;
+      d.sy = in.y0 / ih.dx_out;
+      const double zl = ih.z / ih.lam;
+      d.kz_turns = (zl - std::floor(zl)) - 0.25;
+      d.scale = p.dx * p.dx / lz;
+      d.x0 = in.x0;
+      d.y0 = in.y0;
+      d.dx_out = ih.dx_out;
+      d.inv2lz = 1.0 / (2.0 * lz);
+      const double j11 = 3.8317059702075125;
+      const double rnull = j11 / M_PI * lz / ap->D;
+      d.rnull2 = rnull * rnull;
+      const double R = 0.5 * ap->D;
+      d.R2_over_lz2 = (R * R / lz) * (R * R / lz);
+      d.t_mtf = 0.5 * (ap->D / lz) * (double)in.M * ih.dx_out;
+      ih.roi_off = roi;
+      roi += (int64_t)in.M * in.M;
+      if (in.M > p.Mmax) p.Mmax = in.M;
+    }
+    p.roi_elems = roi;
+
+    // stripe and chunk schedule
+    const bool split = o.path == FZP_PATH_SPLIT_BF16;
+    p.S = o.stripe_rows > 0 ? o.stripe_rows : (split ? 128 : 64);
+    if (split && p.S != 64 && p.S != 128 && p.S != 256) {
+      delete h;
+      return fail(FZP_E_INVAL, "fzp_plan: split path stripe_rows must be 64, 128 or 256");
+    }
+    if (split)
+      for (const auto &ih : p.inst)
+        if (ih.in.M % 32 != 0) {
+          delete h;
+          return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path needs M to be a multiple of 32");
+        }
+    const size_t tbytes = split ? sizeof(float) * 2 : sizeof(double) * 2;
+    if (o.chunk_rows > 0) {
+      p.chunk_rows = o.chunk_rows;
+    } else {
+      const size_t budget = (size_t)512 << 20;  // T buffer target
+      int64_t c = (int64_t)(budget / ((size_t)p.Mmax * tbytes));
+      c = c / p.S * p.S;
+      if (c < p.S) c = p.S;
+      p.chunk_rows = c < N ? c : N;
+    }
+    if (split) p.chunk_rows = (p.chunk_rows + p.S - 1) / p.S * p.S;
+
+    // workspace layout
+    size_t off = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      InstHost &ih = p.inst[k];
+      ih.off_Hx = off;
+      off = align256(off + fzp::kFftLen * sizeof(double2));
+      ih.off_Hy = off;
+      off = align256(off + fzp::kFftLen * sizeof(double2));
+      ih.off_Dt = off;
+      off = align256(off + fzp::kFftLen * sizeof(double2));
+      ih.off_Qx = off;
+      off = align256(off + (size_t)ih.in.M * sizeof(double2));
+      ih.off_Qy = off;
+      off = align256(off + (size_t)ih.in.M * sizeof(double2));
+      ih.off_cr = off;
+      off = align256(off + (size_t)(ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
+      ih.table_owner = k;
+      ih.off_A = 0;
+    }
+    if (split) {
+      const int64_t npad = (N + 63) / 64 * 64;
+      for (int k = 0; k < n_inst; ++k) {
+        InstHost &ih = p.inst[k];
+        // instances with the same ROI grid and lambda z share one operand table
+        for (int k2 = 0; k2 < k; ++k2) {
+          const InstHost &o2 = p.inst[k2];
+          if (o2.table_owner == k2 && o2.dev.M == ih.dev.M && o2.dev.alpha == ih.dev.alpha &&
+              o2.dev.beta == ih.dev.beta && o2.dev.sx == ih.dev.sx) {
+            ih.table_owner = k2;
+            ih.off_A = o2.off_A;
+            break;
+          }
+        }
+        if (ih.table_owner == k) {
+          ih.off_A = off;
+          off = align256(off + (size_t)2 * 2 * ih.in.M * npad * sizeof(uint16_t));
+        }
+        ih.dev.Npad = npad;
+      }
+    }
+    p.off_T = off;
+    p.T_bytes = align256((size_t)p.chunk_rows * p.Mmax * tbytes);
+    off += p.T_bytes;
+    p.off_scratch = off;
+    p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
+    off += p.scratch_bytes;
+    p.ws_bytes = off;
+    if (o.workspace_limit > 0 && p.ws_bytes > o.workspace_limit) {
+      const size_t need = p.ws_bytes;
+      delete h;
+      return fail(FZP_E_NOMEM, "fzp_plan: workspace of " + std::to_string(need) + " bytes exceeds the limit");
+    }
+    *out = h;
+    return FZP_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(FZP_E_NOMEM, "fzp_plan: out of host memory");
+  } catch (const std::exception &e) {
+    return fail(FZP_E_INVAL, std::string("fzp_plan: ") + e.what());
+  } catch (...) {
+    return fail(FZP_E_INVAL, "fzp_plan: unknown error");
+  }
+}
+
+extern "C" fzp_status_t fzp_plan_workspace_size(fzp_plan_t p, size_t *bytes) {
+  if (!p || !bytes) return fail(FZP_E_INVAL, "fzp_plan_workspace_size: NULL argument");
+  *bytes = p->plan.ws_bytes;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_roi_elements(fzp_plan_t p, int64_t *n) {
+  if (!p || !n) return fail(FZP_E_INVAL, "fzp_roi_elements: NULL argument");
+  *n = p->plan.roi_elems;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_roi_offset(fzp_plan_t p, int32_t k, int64_t *off) {
+  if (!p || !off || k < 0 || k >= (int32_t)p->plan.inst.size()) return fail(FZP_E_INVAL, "fzp_roi_offset: bad argument");
+  *off = p->plan.inst[k].roi_off;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64_t *chunk_rows,
+                                      int32_t *stripe_rows, int32_t *path, int64_t *disc_samples, double *kappa) {
+  if (!p) return fail(FZP_E_INVAL, "fzp_plan_info: NULL plan");
+  const Plan &pl = p->plan;
+  if (fft_len) *fft_len = fzp::kFftLen;
+  if (block) *block = pl.inst[0].dev.B;
+  if (chunk_rows) *chunk_rows = pl.chunk_rows;
+  if (stripe_rows) *stripe_rows = pl.S;
+  if (path) *path = pl.opt.path;
+  if (disc_samples) *disc_samples = pl.disc_samples;
+  if (kappa) *kappa = pl.kappa;
+  return FZP_OK;
+}
+
+extern "C" void fzp_destroy(fzp_plan_t p) { delete p; }
+
+namespace {
+
+fzp_status_t hip_fail(const char *what, hipError_t e) {
+  return fail(FZP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device pointers of the tables of instance k inside workspace ws.
+void bind_tables(Plan &p, char *ws) {
+  for (auto &ih : p.inst) {
+    ih.dev.Hx = (const double2 *)(ws + ih.off_Hx);
+    ih.dev.Hy = (const double2 *)(ws + ih.off_Hy);
+    ih.dev.Dt = (const double2 *)(ws + ih.off_Dt);
+    ih.dev.Qx = (const double2 *)(ws + ih.off_Qx);
+    ih.dev.Qy = (const double2 *)(ws + ih.off_Qy);
+    ih.dev.cr = (const fzp::CreaseDev *)(ws + ih.off_cr);
+    ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream) {
+  if (!h || !workspace) return fail(FZP_E_INVAL, "fzp_prepare: NULL argument");
+  if (((uintptr_t)workspace & 255) != 0) return fail(FZP_E_INVAL, "fzp_prepare: workspace must be 256-byte aligned");
+  try {
+    Plan &p = h->plan;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    bind_tables(p, ws);
+    for (size_t k = 0; k < p.inst.size(); ++k) {
+      InstHost &ih = p.inst[k];
+      // crease constants
+      std::vector<fzp::CreaseDev> cd(ih.creases.size() + 1);
+      for (size_t c = 0; c < ih.creases.size(); ++c) {
+        const fzp_crease_t &cr = ih.creases[c];
+        const double sigma = cr.width / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        cd[c].c = std::cos(cr.theta);
+        cd[c].s = std::sin(cr.theta);
+        cd[c].rho = cr.offset;
+        cd[c].inv2s2 = 1.0 / (2.0 * sigma * sigma);
+        cd[c].h_over_lambda = cr.height / ih.lam;
+      }
+      hipError_t e = hipMemcpyAsync(ws + ih.off_cr, cd.data(), cd.size() * sizeof(fzp::CreaseDev),
+                                    hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail("fzp_prepare: crease upload", e);
+      // pageable source: make sure the copy has consumed cd before it goes out of scope
+      e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail("fzp_prepare: synchronize", e);
+      e = fzp::launch_build_tables(p, ih, ws, st);
+      if (e != hipSuccess) return hip_fail("fzp_prepare: table kernel", e);
+      if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.table_owner == (int32_t)k) {
+        e = fzp::launch_build_split_table(p, ih, ws, st);
+        if (e != hipSuccess) return hip_fail("fzp_prepare: split table kernel", e);
+      }
+    }
+    p.prepared_ws = workspace;
+    return FZP_OK;
+  } catch (const std::exception &e) {
+    return fail(FZP_E_INVAL, std::string("fzp_prepare: ") + e.what());
+  } catch (...) {
+    return fail(FZP_E_INVAL, "fzp_prepare: unknown error");
+  }
+}
+
+extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, double *roi_dev, int64_t row_begin,
+                                                int64_t row_end, int32_t accumulate, void *stream) {
+  if (!h || !workspace || !roi_dev) return fail(FZP_E_INVAL, "fzp_propagate_roi_range: NULL argument");
+  Plan &p = h->plan;
+  if (row_begin < 0 || row_end < row_begin || row_end > p.ap.N)
+    return fail(FZP_E_INVAL, "fzp_propagate_roi_range: need 0 <= row_begin <= row_end <= N");
+  if (p.prepared_ws != workspace) {
+    const fzp_status_t s = fzp_prepare(h, workspace, stream);
+    if (s != FZP_OK) return s;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  hipError_t e;
+  if (!accumulate) {
+    e = fzp::launch_zero(roi_dev, 2 * p.roi_elems, st);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: zero", e);
+  }
+  const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
+  void *T = ws + p.off_T;
+  for (auto &ih : p.inst) {
+    double2 *roi = (double2 *)roi_dev + ih.roi_off;
+    // chunks are aligned to multiples of chunk_rows from row 0
+    int64_t c0 = row_begin / p.chunk_rows * p.chunk_rows;
+    for (; c0 < row_end; c0 += p.chunk_rows) {
+      const int64_t r0 = c0 > row_begin ? c0 : row_begin;
+      const int64_t r1 = c0 + p.chunk_rows < row_end ? c0 + p.chunk_rows : row_end;
+      if (r1 <= r0) continue;
+      hipEvent_t ea = nullptr, eb = nullptr;
+      size_t first = 0;
+      if (p.profile) {
+        e = take_events(p, ea, eb, first);
+        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
+        (void)hipEventRecord(ea, st);
+      }
+      if (split)
+        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, st);
+      else
+        e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
+      if (p.profile) {
+        (void)hipEventRecord(eb, st);
+        p.ev_marks.emplace_back(first, 0);
+        e = take_events(p, ea, eb, first);
+        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
+        (void)hipEventRecord(ea, st);
+      }
+      e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, roi, st);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
+      if (p.profile) {
+        (void)hipEventRecord(eb, st);
+        p.ev_marks.emplace_back(first, 1);
+      }
+    }
+  }
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_propagate_roi(fzp_plan_t h, void *workspace, double *roi_dev, void *stream) {
+  if (!h) return fail(FZP_E_INVAL, "fzp_propagate_roi: NULL plan");
+  return fzp_propagate_roi_range(h, workspace, roi_dev, 0, h->plan.ap.N, 0, stream);
+}
+
+extern "C" fzp_status_t fzp_metrics(fzp_plan_t h, void *workspace, const double *roi_dev, fzp_metrics_t *out_host,
+                                    void *stream) {
+  if (!h || !workspace || !roi_dev || !out_host) return fail(FZP_E_INVAL, "fzp_metrics: NULL argument");
+  Plan &p = h->plan;
+  if (p.prepared_ws != workspace) {
+    const fzp_status_t s = fzp_prepare(h, workspace, stream);
+    if (s != FZP_OK) return s;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  char *scratch = ws + p.off_scratch;
+  fzp_metrics_t *dev_out = (fzp_metrics_t *)(scratch + p.scratch_bytes - 256);
+  for (size_t k = 0; k < p.inst.size(); ++k) {
+    const InstHost &ih = p.inst[k];
+    hipError_t e = fzp::launch_metrics(ih.dev, (const double2 *)roi_dev + ih.roi_off, (double)p.disc_samples,
+                                       scratch, dev_out, st);
+    if (e != hipSuccess) return hip_fail("fzp_metrics: kernels", e);
+    e = hipMemcpyAsync(&out_host[k], dev_out, sizeof(fzp_metrics_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail("fzp_metrics: copy", e);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail("fzp_metrics: synchronize", e);
+  }
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_profile_enable(fzp_plan_t h, int32_t on) {
+  if (!h) return fail(FZP_E_INVAL, "fzp_profile_enable: NULL plan");
+  h->plan.profile = on != 0;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_profile_read(fzp_plan_t h, double *row_ms, int64_t *row_launches, double *col_ms,
+                                         int64_t *col_launches, int32_t reset) {
+  if (!h) return fail(FZP_E_INVAL, "fzp_profile_read: NULL plan");
+  Plan &p = h->plan;
+  for (const auto &mk : p.ev_marks) {
+    hipError_t e = hipEventSynchronize(p.ev_pool[mk.first + 1]);
+    if (e != hipSuccess) return hip_fail("fzp_profile_read: synchronize", e);
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, p.ev_pool[mk.first], p.ev_pool[mk.first + 1]);
+    if (e != hipSuccess) return hip_fail("fzp_profile_read: elapsed", e);
+    if (mk.second == 0) {
+      p.row_ms += ms;
+      ++p.row_n;
+    } else {
+      p.col_ms += ms;
+      ++p.col_n;
+    }
+  }
+  p.ev_marks.clear();
+  p.ev_used = 0;
+  if (row_ms) *row_ms = p.row_ms;
+  if (row_launches) *row_launches = p.row_n;
+  if (col_ms) *col_ms = p.col_ms;
+  if (col_launches) *col_launches = p.col_n;
+  if (reset) {
+    p.row_ms = p.col_ms = 0.0;
+    p.row_n = p.col_n = 0;
+  }
+  return FZP_OK;
+}

@@ -1,0 +1,113 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every function that include/fzp.h declares, and validates its arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2609_01978_amd as P
+from paper_2609_01978_amd import _lib as L
+from oracle import fzp_oracle as O
+from fzp_inputs import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LAM0 = 632.8e-9
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fzp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fzp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = P.load_library()
+    declared = header_functions()
+    assert "fzp_plan" in declared and "fzp_propagate_roi" in declared and "fzp_metrics" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(declared) == sorted(P.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(L.Aperture) == 48
+    assert ctypes.sizeof(L.Crease) == 32
+    assert ctypes.sizeof(L.Instance) == 56
+    assert ctypes.sizeof(L.Options) == 32
+    assert ctypes.sizeof(L.Metrics) == 64
+
+
+def ap_of(name):
+    w = workload(name)
+    return dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"]), w
+
+
+def test_plan_facts_match_oracle():
+    for name in ("fzp2mm", "fzp20mm"):
+        ap, w = ap_of(name)
+        plan = P.Plan(ap, [dict(lam=w["lambda0"], M=w["M"])])
+        info = plan.info()
+        oa = O.Aperture(D=ap["D"], f0=ap["f0"], lambda0=ap["lambda0"], N=ap["N"])
+        assert info["disc_samples"] == O.incident_count(oa)
+        assert info["kappa"] == oa.dx * oa.dx / (4.0 * oa.lambda0 * oa.f0)
+        assert info["block"] == 4096 - w["M"] + 1
+        assert plan.roi_elements == w["M"] ** 2
+
+
+def test_sampling_limit_eq6():
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=1024), [dict(lam=LAM0, M=64)])
+    assert e.value.status == P.FZP_E_SAMPLING
+    # 2 samples per outermost zone is the limit: N = 2 D^2/(lambda f) passes
+    N = int(2 * (2e-3) ** 2 / (LAM0 * 10e-3)) + 1
+    P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N), [dict(lam=LAM0, M=64)])
+    P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=64), [dict(lam=LAM0, M=64)], allow_undersampled=True)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ap=dict(D=-1.0)), dict(ap=dict(N=0)), dict(ap=dict(N=(1 << 21) + 1)), dict(ap=dict(centre_open=2)),
+    dict(inst=dict(M=1)), dict(inst=dict(M=4096)), dict(inst=dict(lam=float("nan"))), dict(inst=dict(z=-1.0)),
+    dict(inst=dict(creases=[(0.0, 0.0, 0.0, 1e-7)])),
+])
+def test_invalid_arguments(bad):
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096)
+    inst = dict(lam=LAM0, M=256)
+    ap.update(bad.get("ap", {}))
+    inst.update(bad.get("inst", {}))
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(ap, [inst])
+    assert e.value.status == P.FZP_E_INVAL
+
+
+def test_workspace_limit_and_split_constraints():
+    ap, w = ap_of("fzp1m")
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    plan = P.Plan(ap, [inst], path="split")
+    need = plan.workspace_size
+    assert need > 4 * 2 ** 30                      # the BF16 hi/lo operand table of the 1 m element
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(ap, [inst], path="split", workspace_limit=need - 1)
+    assert e.value.status == P.FZP_E_NOMEM
+    P.Plan(ap, [inst], path="split", workspace_limit=need)
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096), [dict(lam=LAM0, M=100)], path="split")
+    assert e.value.status == P.FZP_E_UNSUPPORTED
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096), [dict(lam=LAM0, M=256)], path="split", stripe_rows=96)
+    assert e.value.status == P.FZP_E_INVAL
+
+
+def test_multi_instance_roi_offsets():
+    ap = dict(D=20e-3, f0=100e-3, lambda0=LAM0, N=32768)
+    Ms = [256, 1024, 512]
+    plan = P.Plan(ap, [dict(lam=600e-9, M=m) for m in Ms])
+    assert plan.roi_elements == sum(m * m for m in Ms)
+    assert [plan.roi_offset(k) for k in range(3)] == [0, 256 ** 2, 256 ** 2 + 1024 ** 2]
+
+
+def test_last_error_is_thread_local_message():
+    lib = P.load_library()
+    with pytest.raises(P.FZPError):
+        P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=0), [dict(lam=LAM0, M=256)])
+    assert b"N must be" in lib.fzp_last_error()

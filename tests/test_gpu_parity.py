@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Full-ROI comparisons at sizes the oracle finishes in seconds; at the full
+workload sizes, sampled stripes of aperture rows (the library's row-range
+call against the oracle's restricted row sum) plus properties that hold at any
+size.  Bars: ROI intensity rel-L2 <= 1e-6 for the FP64 Bluestein path and
+<= 1e-4 for the split-BF16 path; FWHM and DE within 0.1 % of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2609_01978_amd as P  # noqa: E402
+from oracle import fzp_oracle as O  # noqa: E402
+from fzp_inputs import crease_draws, workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+LAM0 = 632.8e-9
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_gpu(ap: dict, insts: list, path="fp64", rows=None, **kw):
+    plan = P.Plan(ap, insts, path=path, **kw)
+    ws, roi = plan.alloc()
+    if rows is None:
+        plan.propagate(ws, roi)
+    else:
+        plan.propagate_range(ws, roi, rows[0], rows[1], accumulate=False)
+    torch.cuda.synchronize()
+    out = [plan.roi_view(roi, k).cpu().numpy() for k in range(len(insts))]
+    return plan, ws, roi, out
+
+
+def oracle_case(ap: dict, inst: dict):
+    a = O.Aperture(D=ap["D"], f0=ap["f0"], lambda0=ap["lambda0"], N=ap["N"], pitch=ap.get("pitch", 0.0),
+                   centre_open=ap.get("centre_open", 0))
+    i = O.Instance(lam=inst["lam"], M=inst["M"], z=inst.get("z", 0.0), x0=inst.get("x0", 0.0),
+                   y0=inst.get("y0", 0.0), half_width=inst.get("half_width", 0.0), creases=inst.get("creases"))
+    return a, i
+
+
+def announce(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Full ROI against the oracle
+# ---------------------------------------------------------------------------
+
+SMALL = [
+    # (name, aperture, instance, allow_undersampled)
+    ("tiny_offcentre_open", dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=777, centre_open=1),
+     dict(lam=560e-9, M=48, x0=1.5e-6, y0=-2.25e-6, half_width=40e-6), True),
+    ("pitch_ragged", dict(D=1e-3, f0=4e-3, lambda0=LAM0, N=1001, pitch=1e-3 / 997),
+     dict(lam=LAM0, M=64, z=4.05e-3), True),
+    ("creases", dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=1536),
+     dict(lam=700e-9, M=96, creases=crease_draws(5, 2e-3, LAM0, 8) * np.array([1, 1, 0.2, 1])), True),
+    ("multi_block_m1024", dict(D=4e-3, f0=20e-3, lambda0=LAM0, N=8192),
+     dict(lam=LAM0, M=1024), False),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_fp64_full_roi_small(case):
+    name, ap, inst, und = case
+    announce(f"fp64 {name} N={ap['N']} M={inst['M']}")
+    plan, ws, roi, (U,) = run_gpu(ap, [inst], allow_undersampled=und)
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=256)
+    assert rel_l2(U, ref) < 1e-9
+    assert rel_l2(O.intensity(U), O.intensity(ref)) < 1e-9
+
+
+def test_fp64_fzp2mm_full_and_metrics():
+    w = workload("fzp2mm")
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    announce("fp64 fzp2mm full ROI + metrics")
+    plan, ws, roi, (U,) = run_gpu(ap, [inst], stripe_rows=w["stripe"])
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    e_int = rel_l2(O.intensity(U), O.intensity(ref))
+    announce(f"fzp2mm intensity rel-L2 {e_int:.3e}")
+    assert e_int <= 1e-6
+    assert rel_l2(U, ref) < 1e-9
+    m = plan.metrics(ws, roi)[0]
+    mo = O.metrics(ref, a, i)
+    for key in ("fwhm_x", "fwhm_y", "de", "strehl", "i_peak", "p_lobe", "p_in"):
+        assert abs(m[key] / mo[key] - 1) < 1e-8, (key, m[key], mo[key])
+    assert abs(m["mtf_half_cut"] / mo["mtf_half_cut"] - 1) < 1e-8
+    # and against the continuous radial reference (finite-zone closed form)
+    h = O.hankel_metrics(a)
+    assert abs(m["fwhm_x"] / h["fwhm"] - 1) < 1e-3 and abs(m["de"] / h["de"] - 1) < 1e-3
+
+
+def test_fp64_bitwise_reproducible_and_ranges_add_up():
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096)
+    inst = dict(lam=LAM0, M=256)
+    plan = P.Plan(ap, [inst], chunk_rows=512)
+    ws, roi = plan.alloc()
+    plan.propagate(ws, roi)
+    a = roi.clone()
+    plan.propagate(ws, roi)
+    torch.cuda.synchronize()
+    assert torch.equal(a, roi)
+    # two ranges split on a chunk boundary reproduce the full run bit for bit
+    plan.propagate_range(ws, roi, 0, 1536, accumulate=False)
+    plan.propagate_range(ws, roi, 1536, 4096, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, roi)
+
+
+def test_split_fzp2mm_vs_fp64_and_oracle():
+    w = workload("fzp2mm")
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    announce("split fzp2mm")
+    _, _, _, (U64,) = run_gpu(ap, [inst])
+    plan, ws, roi, (Us,) = run_gpu(ap, [inst], path="split", stripe_rows=128)
+    e = rel_l2(O.intensity(Us), O.intensity(U64))
+    announce(f"split vs fp64 intensity rel-L2 {e:.3e}")
+    assert e <= 1e-4
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    assert rel_l2(O.intensity(Us), O.intensity(ref)) <= 1e-4
+    m = plan.metrics(ws, roi)[0]
+    mo = O.metrics(ref, a, i)
+    assert abs(m["fwhm_x"] / mo["fwhm_x"] - 1) < 1e-3 and abs(m["de"] / mo["de"] - 1) < 1e-3
+
+
+def test_split_creases_small():
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
+    cr = crease_draws(7, 2e-3, LAM0, 8)
+    inst = dict(lam=600e-9, M=128, creases=cr)
+    _, _, _, (U64,) = run_gpu(ap, [inst])
+    _, _, _, (Us,) = run_gpu(ap, [inst], path="split")
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    assert rel_l2(O.intensity(U64), O.intensity(ref)) < 1e-9
+    assert rel_l2(O.intensity(Us), O.intensity(U64)) <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Full workload sizes: sampled stripes and properties
+# ---------------------------------------------------------------------------
+
+def _sampled_stripes(name, path, stripes):
+    w = workload(name)
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"])
+    ws, roi = plan.alloc()
+    a, i = oracle_case(ap, inst)
+    S = w["stripe"]
+    for j0 in stripes:
+        announce(f"{name} {path} stripe rows {j0}..{j0 + S}")
+        plan.propagate_range(ws, roi, j0, j0 + S, accumulate=False)
+        torch.cuda.synchronize()
+        U = plan.roi_view(roi, 0).cpu().numpy()
+        ref = O.propagate(a, i, method="bluestein", rows=(j0, j0 + S), stripe=32)
+        e = rel_l2(U, ref)
+        announce(f"  complex rel-L2 {e:.3e}")
+        assert e <= (1e-6 if path == "fp64" else 1e-4)
+
+
+def test_fzp20mm_sampled_stripes_fp64():
+    N = workload("fzp20mm")["N"]
+    _sampled_stripes("fzp20mm", "fp64", [N // 2 - 128, 1024, N - 3 * 256])
+
+
+def test_fzp20mm_sampled_stripes_split():
+    N = workload("fzp20mm")["N"]
+    _sampled_stripes("fzp20mm", "split", [N // 2 - 128, 3072])
+
+
+def test_fzp1m_sampled_stripes_fp64():
+    N = workload("fzp1m")["N"]
+    _sampled_stripes("fzp1m", "fp64", [N // 2 - 64, 100 * 128])
+
+
+def test_fzp1m_sampled_stripes_split():
+    N = workload("fzp1m")["N"]
+    _sampled_stripes("fzp1m", "split", [N // 2 - 64])
