@@ -209,9 +209,12 @@ __device__ __forceinline__ double2 to_c64(float2 v) { return make_double2((doubl
 // Column pass: one work-group per ROI column q (grid-stride).  Adds
 // F[p,q] Qy[p] sum_blocks(...) into roi[p][q]; each ROI element is owned by one
 // work-group, so the float64 sum over chunks is a fixed-order sequence.
+// T holds nseg partial row-pass results (K segments of the split path),
+// seg_stride complex elements apart; they are summed here in float64.
 template <int NQ, typename TT>
 __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t row_begin, int64_t row_end,
-                                                             const TT *__restrict__ T, double2 *__restrict__ roi) {
+                                                             const TT *__restrict__ T, int nseg, int64_t seg_stride,
+                                                             double2 *__restrict__ roi) {
   __shared__ double2 s_lds[kLdsN];
   const int t = threadIdx.x;
   const Tw tw = fft_twiddles();
@@ -219,7 +222,10 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   for (int q = blockIdx.x; q < M; q += gridDim.x) {
     double2 acc[NQ];
     bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, [&](int64_t j) -> double2 {
-      return to_c64(T[(j - row_begin) * (int64_t)M + q]);
+      const TT *src = T + (j - row_begin) * (int64_t)M + q;
+      double2 g = to_c64(src[0]);
+      for (int sgi = 1; sgi < nseg; ++sgi) g = cadd(g, to_c64(src[sgi * seg_stride]));
+      return g;
     });
     const double xq = d.x0 + ((double)q - 0.5 * (double)M) * d.dx_out;
 #pragma unroll
@@ -288,16 +294,16 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
 }
 
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T, bool t_is_fp32,
-                           double2 *roi, hipStream_t st) {
+                           int nseg, int64_t seg_stride, double2 *roi, hipStream_t st) {
   if (row_end <= row_begin) return hipSuccess;
   const int grid = d.M;
 #define FZP_COL(NQ)                                                                                         \
   if (t_is_fp32)                                                                                            \
     hipLaunchKernelGGL((k_col_pass<NQ, float2>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, \
-                       (const float2 *)T, roi);                                                             \
+                       (const float2 *)T, nseg, seg_stride, roi);                                           \
   else                                                                                                      \
     hipLaunchKernelGGL((k_col_pass<NQ, double2>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, \
-                       (const double2 *)T, roi);
+                       (const double2 *)T, 1, (int64_t)0, roi);
   if (d.M <= 256) {
     FZP_COL(1)
   } else if (d.M <= 512) {

@@ -78,6 +78,7 @@ struct Plan {
   std::vector<InstHost> inst;
   int64_t roi_elems;
   size_t off_T, T_bytes;
+  size_t off_bits = 0, bits_bytes = 0;
   size_t off_scratch, scratch_bytes;
   size_t ws_bytes;
   const void *prepared_ws = nullptr;
@@ -97,10 +98,15 @@ hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws,
 hipError_t launch_zero(double *buf, int64_t n_doubles, hipStream_t st);
 hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row_end, double2 *T,
                                 hipStream_t st);
+// Split row pass: writes split_segments(d) partial results, each chunk_rows x M
+// complex float32, seg_stride complex elements apart.
+int split_segments(const InstDev &d);
+constexpr int64_t kSplitSegLen = 65536;  // K columns per split-path segment
+size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows);  // zone-mask bit buffer of one chunk
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
-                                 float2 *T, hipStream_t st);
+                                 float2 *T, int64_t seg_stride, uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,
-                           bool t_is_fp32, double2 *roi, hipStream_t st);
+                           bool t_is_fp32, int nseg, int64_t seg_stride, double2 *roi, hipStream_t st);
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,
                           fzp_metrics_t *dev_out, hipStream_t st);
 size_t metrics_scratch_bytes(int32_t M);

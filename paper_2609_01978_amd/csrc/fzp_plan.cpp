@@ -207,15 +207,22 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     }
     if (split)
       for (const auto &ih : p.inst)
-        if (ih.in.M % 32 != 0) {
+        if (ih.in.n_creases > 0) {
           delete h;
-          return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path needs M to be a multiple of 32");
+          return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path does not take creases yet");
         }
-    const size_t tbytes = split ? sizeof(float) * 2 : sizeof(double) * 2;
+    if (split)
+      for (const auto &ih : p.inst)
+        if (ih.in.M % 16 != 0) {
+          delete h;
+          return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path needs M to be a multiple of 16");
+        }
+    const int64_t nseg = split ? (N + fzp::kSplitSegLen - 1) / fzp::kSplitSegLen : 1;
+    const size_t tbytes = split ? sizeof(float) * 2 * (size_t)nseg : sizeof(double) * 2;
     if (o.chunk_rows > 0) {
       p.chunk_rows = o.chunk_rows;
     } else {
-      const size_t budget = (size_t)512 << 20;  // T buffer target
+      const size_t budget = (size_t)(split ? 1024 : 512) << 20;  // T buffer target
       int64_t c = (int64_t)(budget / ((size_t)p.Mmax * tbytes));
       c = c / p.S * p.S;
       if (c < p.S) c = p.S;
@@ -266,6 +273,11 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     p.off_T = off;
     p.T_bytes = align256((size_t)p.chunk_rows * p.Mmax * tbytes);
     off += p.T_bytes;
+    if (split) {
+      p.off_bits = off;
+      p.bits_bytes = align256(fzp::split_bits_bytes(p.inst[0].dev, p.chunk_rows));
+      off += p.bits_bytes;
+    }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
     off += p.scratch_bytes;
@@ -418,8 +430,11 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
         if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
         (void)hipEventRecord(ea, st);
       }
+      const int nseg = split ? fzp::split_segments(ih.dev) : 1;
+      const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
       if (split)
-        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, st);
+        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (uint32_t *)(ws + p.off_bits),
+                                       st);
       else
         e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
@@ -430,7 +445,7 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
         if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
         (void)hipEventRecord(ea, st);
       }
-      e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, roi, st);
+      e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, nseg, seg_stride, roi, st);
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
       if (p.profile) {
         (void)hipEventRecord(eb, st);

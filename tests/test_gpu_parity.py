@@ -134,6 +134,22 @@ def test_split_fzp2mm_vs_fp64_and_oracle():
     assert abs(m["fwhm_x"] / mo["fwhm_x"] - 1) < 1e-3 and abs(m["de"] / mo["de"] - 1) < 1e-3
 
 
+@pytest.mark.parametrize("N,M", [(3000, 48), (2500, 128), (4096, 384)])
+def test_split_shapes_ragged(N, M):
+    """Row tiles with a ragged tail, column tiles wider than 2M, several K stages."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N)
+    inst = dict(lam=LAM0, M=M)
+    announce(f"split N={N} M={M}")
+    _, _, _, (U64,) = run_gpu(ap, [inst], allow_undersampled=True)
+    _, _, _, (Us,) = run_gpu(ap, [inst], path="split", allow_undersampled=True)
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    assert rel_l2(O.intensity(U64), O.intensity(ref)) < 1e-9
+    e = rel_l2(O.intensity(Us), O.intensity(ref))
+    announce(f"  split vs oracle intensity rel-L2 {e:.3e}")
+    assert e <= 1e-4
+
+
 def test_split_creases_small():
     ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
     cr = crease_draws(7, 2e-3, LAM0, 8)
