@@ -10,10 +10,14 @@
 // parts; the mask is exact in BF16, so T = mask.A_hi + mask.A_lo (two MFMA
 // products, float32 accumulation) carries A to about 2^-16 relative.
 //
-// Table layout: At[plane][c][i], plane 0 = hi, 1 = lo, c = 2q + {0: re, 1: im},
-// i = 0 .. Npad-1 (zero beyond N), so an MFMA B operand (8 consecutive k of one
-// column) is one 16-byte load and the accumulator columns interleave re/im as
-// the float2 T buffer does.
+// Table layout, blocked by 32 aperture columns:
+//   At[plane][i / 32][c][i % 32],  plane 0 = hi, 1 = lo,  c = 2q + {0: re, 1: im},
+// i = 0 .. Npad-1 (zero beyond N).  One pipeline stage of a column tile (32 k
+// of 128 columns) is then one contiguous 8 KiB slab per plane, an MFMA B
+// operand (8 consecutive k of one column) is one 16-byte chunk, and the
+// accumulator columns interleave re/im as the float2 T buffer does.
+
+#include <cmath>
 
 #include "fzp_device.h"
 #include "fzp_internal.h"
@@ -52,15 +56,18 @@ __global__ __launch_bounds__(256) void k_build_split_table(InstDev d, uint16_t *
     lr = bf16_rne((float)(a.x - bf16_to_double(hr)));
     li = bf16_rne((float)(a.y - bf16_to_double(hi_)));
   }
-  At[(int64_t)(2 * q) * d.Npad + i] = hr;
-  At[(int64_t)(2 * q + 1) * d.Npad + i] = hi_;
-  At[plane + (int64_t)(2 * q) * d.Npad + i] = lr;
-  At[plane + (int64_t)(2 * q + 1) * d.Npad + i] = li;
+  const int64_t blk = (i >> 5) * (int64_t)(2 * M) * 32 + (i & 31);
+  At[blk + (int64_t)(2 * q) * 32] = hr;
+  At[blk + (int64_t)(2 * q + 1) * 32] = hi_;
+  At[plane + blk + (int64_t)(2 * q) * 32] = lr;
+  At[plane + blk + (int64_t)(2 * q + 1) * 32] = li;
 }
 
 // ---------------------------------------------------------------------------
-// Zone-mask bits of a chunk of aperture rows: bits[r - row_begin][w], bit e of
-// word w is the mask at column 32 w + e (zero outside the row's disc chord).
+// Zone-mask bits of a chunk of aperture rows, word-major: bits[w][r - row_begin]
+// (row stride `rows`), bit e of word w is the mask at column 32 w + e (zero
+// outside the row's disc chord); one pipeline stage of a row tile is then one
+// contiguous run of words.
 // K = c_i^2 + c_j^2 is exact in float64 and zone = floor(K kappa) is the same
 // single float64 product the reference rule uses (Sec. 2.2, Eq. 4).  Each
 // element is evaluated once here instead of once per GEMM column tile.
@@ -71,37 +78,39 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
   const int Nm1 = (int)(N - 1);
   const double kappa = d.kappa;
   const uint32_t flip = d.centre_open ? 0xffffffffu : 0u;
-  for (int64_t row = row_begin + blockIdx.x; row < row_end; row += gridDim.x) {
-    const double cj = (double)(2 * row - N + 1);
-    const double bj = cj * cj;
-    int rlo = 0, rhi = 0;
-    const double rem = d.kmax - bj;
-    if (rem >= 0.0) {
-      int m = (int)sqrt(rem);
-      while ((double)(m + 1) * (double)(m + 1) <= rem) ++m;
-      while (m > 0 && (double)m * (double)m > rem) --m;
-      rlo = (Nm1 - m + 1) >> 1;
-      rhi = ((Nm1 + m) >> 1) + 1;
-    }
-    uint32_t *out = bits + (row - row_begin) * (int64_t)W;
-    for (int w = threadIdx.x; w < W; w += blockDim.x) {
-      const int i0 = 32 * w;
-      uint32_t v = 0;
-      if (i0 < rhi && i0 + 32 > rlo) {
-        double ci = (double)(2 * i0 - Nm1);
+  const int64_t rows = row_end - row_begin;
+  const int64_t rl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // thread = one row
+  if (rl >= rows) return;
+  const int64_t row = row_begin + rl;
+  const double cj = (double)(2 * row - N + 1);
+  const double bj = cj * cj;
+  int rlo = 0, rhi = 0;
+  const double rem = d.kmax - bj;
+  if (rem >= 0.0) {
+    int m = (int)sqrt(rem);
+    while ((double)(m + 1) * (double)(m + 1) <= rem) ++m;
+    while (m > 0 && (double)m * (double)m > rem) --m;
+    rlo = (Nm1 - m + 1) >> 1;
+    rhi = ((Nm1 + m) >> 1) + 1;
+  }
+  const int w0 = blockIdx.y * 64, w1 = min(w0 + 64, W);
+  for (int w = w0; w < w1; ++w) {
+    const int i0 = 32 * w;
+    uint32_t v = 0;
+    if (i0 < rhi && i0 + 32 > rlo) {
+      double ci = (double)(2 * i0 - Nm1);
 #pragma unroll
-        for (int e = 0; e < 32; ++e) {
-          const double K = fma(ci, ci, bj);
-          const int zone = (int)(K * kappa);
-          v |= ((uint32_t)zone & 1u) << e;
-          ci += 2.0;
-        }
-        const int lo = min(max(rlo - i0, 0), 32), hi = min(max(rhi - i0, 0), 32);
-        const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-        v = (v ^ flip) & valid;
+      for (int e = 0; e < 32; ++e) {
+        const double K = fma(ci, ci, bj);
+        const int zone = (int)(K * kappa);
+        v |= ((uint32_t)zone & 1u) << e;
+        ci += 2.0;
       }
-      out[w] = v;
+      const int lo = min(max(rlo - i0, 0), 32), hi = min(max(rhi - i0, 0), 32);
+      const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+      v = (v ^ flip) & valid;
     }
+    bits[(int64_t)w * rows + rl] = v;
   }
 }
 
@@ -111,46 +120,58 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
 // of the tile's rows).  8 waves in a 4 (rows) x 2 (columns) grid, each wave
 // 128 rows x 64 columns = 4 x 2 MFMA 32x32 blocks, 128 float32 accumulators
 // per lane.  The tall tile (512 rows) gives 512 flops per byte of operand
-// slab, above the BF16-MFMA / HBM ridge even without cache reuse.  K advances in stages of kKT = 32 columns (two MFMA K-steps).
-// Pipeline, one barrier per stage s; all global traffic is direct
-// (register-free) global -> LDS copies, so no wave ever waits on a load it
-// has just issued:
-//   - the hi/lo operand slab of stage s+2 and the mask-bit words of stage s+3
-//     are copied into LDS ring slots freed by the previous barrier,
-//   - the MFMAs of stage s run on the LDS copies of stage s,
-//   - the bits of stage s+1 (copied two stages earlier) are expanded to BF16
-//     into the other mask buffer,
-//   - the barrier waits only for the copies issued one stage earlier.
+// slab, above the BF16-MFMA / HBM ridge even without cache reuse.
+//
+// K advances in stages of kKT = 32 columns (two MFMA K-steps).  All global
+// traffic is direct (register-free) global -> LDS copies into 4-deep rings,
+// issued kAhead = 3 stages before use, so no wave waits on a load it has
+// just issued; one barrier per stage:
+//   - copy the hi/lo operand slab and the mask-bit words of stage s+3,
+//   - each lane expands the mask bits of its own 4 rows for stage s straight
+//     into MFMA A operands (no LDS round trip for the mask),
+//   - 32 MFMAs of stage s on the LDS slab,
+//   - wait for the copies issued two stages ago, barrier.
 // Each K segment's partial sum is written in float32 and the column pass adds
 // the segments in float64, which bounds the float32 accumulation length.
 //
-// LDS rows are 64 bytes (32 BF16); the four 16-byte chunks of row r sit in
-// the order chunk ^ swz(r), which spreads both the MFMA operand reads (32
-// consecutive rows, one chunk) and the row writes over all banks without
-// padding: 2 mask buffers + 3 slab buffers + 3 bit-word slots = 118 KiB.
+// LDS slab rows are 64 bytes (32 BF16); the four 16-byte chunks of row r sit
+// in the order chunk ^ swz(r), which keeps the MFMA operand reads (32
+// consecutive rows, one chunk) free of bank conflicts without padding.
 // ---------------------------------------------------------------------------
 constexpr int kThreads = 512;
 constexpr int kTR = 512;     // rows per tile
 constexpr int kTC = 128;     // real columns per tile (64 complex ROI columns)
 constexpr int kKT = 32;      // K columns per pipeline stage
-constexpr int kRowB = 64;    // LDS bytes per row of a stage
-constexpr int kMaskBytes = kTR * kRowB;            // 32768
+constexpr int kRowB = 64;    // LDS bytes per slab row of a stage
 constexpr int kBBytes = 2 * kTC * kRowB;           // 16384 (hi and lo planes)
-constexpr int kBitsBytes = 8 * 64 * 4;           // one dword copy per lane of each wave
-constexpr int kMaskBufs = 2, kBBufs = 3, kBitsBufs = 3;
-constexpr int kLdsBytes = kMaskBufs * kMaskBytes + kBBufs * kBBytes + kBitsBufs * kBitsBytes;  // 120832
+constexpr int kBitsBytes = kTR * 4;                // one mask word per tile row
+constexpr int kRing = 4, kAhead = 3;
+constexpr int kLdsBytes = kRing * (kBBytes + kBitsBytes);  // 73728
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 __device__ __forceinline__ u32x4 lds_ld16(const char *p) { return *(const u32x4 *)p; }
-__device__ __forceinline__ void lds_st16(char *p, u32x4 v) { *(u32x4 *)p = v; }
 
-// Wait until at most 3 vector-memory operations are outstanding - every wave
-// issues exactly 3 copies per stage, so this completes all copies issued
-// before the current stage - and this wave's LDS writes are done, then the
-// work-group barrier.  One asm statement, so that the compiler does not put
-// a blanket wait for all outstanding copies in front of the barrier.
+// Every wave issues exactly 3 copies per stage; waiting until at most 6 are
+// outstanding completes the copies issued two stages ago (those of the next
+// stage), then the work-group barrier makes them visible.  One asm statement,
+// so that the compiler does not put a wait for all outstanding copies in
+// front of the barrier.
 __device__ __forceinline__ void stage_barrier() {
-  asm volatile("s_waitcnt vmcnt(3) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// 8 mask bits (one byte, column order) -> 8 packed BF16 values (1.0 / 0).
+// y = x | x << 15 puts bit 2p at bit 2p and bit 2p+1 at bit 2p+16, so
+// (y >> 2p) & 0x10001 is the pair (b_2p, b_2p+1) as two 16-bit integers,
+// and multiplying by 0x3f80 turns each 1 into BF16 1.0.
+__device__ __forceinline__ bf16x8 expand8(uint32_t x) {
+  const uint32_t y = x | (x << 15);
+  u32x4 v;
+  v[0] = (y & 0x10001u) * 0x3f80u;
+  v[1] = ((y >> 2) & 0x10001u) * 0x3f80u;
+  v[2] = ((y >> 4) & 0x10001u) * 0x3f80u;
+  v[3] = ((y >> 6) & 0x10001u) * 0x3f80u;
+  return __builtin_bit_cast(bf16x8, v);
 }
 
 // Disc chord of the tile rows [r0, r1] (union = chord of the row nearest the axis),
@@ -174,26 +195,28 @@ __device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t
 }
 
 __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
-                                                                int n_rt, int n_ct, int n_seg,
+                                                                int n_rt, int n_ct, int seg_lo, int n_seg,
                                                                 const uint32_t *__restrict__ bits, int W,
-                                                                float *__restrict__ T, int64_t seg_stride_f) {
+                                                                int64_t bits_rows, float *__restrict__ T,
+                                                                int64_t seg_stride_f) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  char *const mbuf = lds;                               // 2 x kMaskBytes
-  char *const bbuf = lds + kMaskBufs * kMaskBytes;      // 3 x kBBytes
-  char *const wbuf = bbuf + kBBufs * kBBytes;           // 3 x kBitsBytes
+  char *const bbuf = lds;                            // kRing x kBBytes
+  char *const wbuf = lds + kRing * kBBytes;          // kRing x kBitsBytes
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  // XCD-aware tile order: work-groups are dealt to the 8 XCDs round robin, so
-  // give each XCD a contiguous run of logical tiles (row tile fastest): the
-  // tiles resident on one XCD share the operand slab in its L2.
+  // XCD-aware tile order.  Work-groups are dealt to the 8 XCDs round robin;
+  // the XCD's own sequence is cut into rounds of 32 (one per CU).  In round
+  // q, XCD x takes the 32 consecutive logical tiles 256 q + 32 x .. (row tile
+  // fastest), so the tiles resident on one XCD share the operand slab in its
+  // L2 while every XCD draws from all K segments (whose work differs).
   const int G = n_rt * n_ct * n_seg;
-  const int per_xcd = (G + 7) / 8;
-  const int g = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int slot = blockIdx.x >> 3;
+  const int g = (slot >> 5) * 256 + (blockIdx.x & 7) * 32 + (slot & 31);
   if (g >= G) return;
   const int rt = g % n_rt;
   const int ct = (g / n_rt) % n_ct;
-  const int seg = g / (n_rt * n_ct);
+  const int seg = seg_lo + g / (n_rt * n_ct);
 
   const int M2 = 2 * d.M;
   const int64_t r0 = row_begin + (int64_t)rt * kTR;
@@ -209,16 +232,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
   if (k_lo < s_lo) k_lo = s_lo;
   if (k_hi > s_hi) k_hi = s_hi;
 
-  // ---- mask role: thread tid expands row tid (all 32 columns of each stage)
-  const int gr = tid;
-  const bool grow_ok = r0 + gr < row_end;
-  // bit-word copy role: wave w copies the words of tile rows [64 w, 64 w + 64),
-  // lane l's word landing at dword tid of the slot; rows past the chunk read
-  // its last row and are zeroed on expansion
+  // ---- bit-word copy role: lane tid copies the word of tile row tid (rows past
+  // the chunk read its last row; their words are zeroed when expanded)
   const int64_t wrow = min(r0 + tid, row_end - 1) - row_begin;
-  const uint32_t *wsrc = bits + wrow * (int64_t)W;
-  const int wslot = tid * 4;
-  const int gsw = swz(gr);
+  const uint32_t *wsrc = bits + wrow;
   // ---- slab-copy role: wave w copies slab rows [32 w, 32 w + 32) (2 direct loads
   // of 16 rows); lane L carries chunk L&3 of row 16 x + L/4 of its block, read
   // from global chunk (L&3) ^ swz(row) so the LDS image is the swizzled layout.
@@ -231,17 +248,20 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
     const int plane = R / kTC, col = R % kTC;
     const int gc = c0 + col < M2 ? c0 + col : 0;
     const int chunk = (lane & 3) ^ swz(R);
-    bsrc[x] = d.A + (int64_t)plane * M2 * d.Npad + (int64_t)gc * d.Npad + 8 * chunk;
+    bsrc[x] = d.A + (int64_t)plane * M2 * d.Npad + (int64_t)gc * 32 + 8 * chunk;
   }
 
   // ---- compute role: wave (wr, wc) covers rows wr*128.., columns wc*64..
   const int wr = wave >> 1, wc = wave & 1;
   const int l32 = lane & 31, lhi = lane >> 5;
   const int lsw = swz(l32);
-  // byte offsets of this lane's operand chunks for K-step ks (row & 31 == l32 everywhere)
+  // byte offsets of this lane's slab chunks for K-step ks (row & 31 == l32 everywhere)
   const int cks0 = ((0 + lhi) ^ lsw) << 4, cks1 = ((2 + lhi) ^ lsw) << 4;
-  const int arow = (wr * 128 + l32) * kRowB;
   const int brow = (wc * 64 + l32) * kRowB;
+  // this lane's 4 mask rows: tile rows wr*128 + rb*32 + l32
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) row_ok |= (r0 + wr * 128 + rb * 32 + l32 < row_end ? 1u : 0u) << rb;
 
   f32x16 acc[4][2];
 #pragma unroll
@@ -252,94 +272,65 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
   if (k_lo < k_hi) {
-    // The pipeline also copies up to three stages past the end: their slab
+    // The pipeline also copies up to kAhead stages past the end: their slab
     // loads are clamped to the table's last slab and their mask is zero.
     const int kb = (int)k_lo;
     const int nst = (int)((k_hi - k_lo) / kKT);
     const int klast = (int)d.Npad - kKT;
-    auto copy_slab = [&](int s) {
+    auto copy_stage = [&](int s) {
       const int k = min(kb + s * kKT, klast);
-      char *dst = bbuf + (s % kBBufs) * kBBytes + wave * 2 * 1024;
+      const int64_t kofs = (int64_t)(k >> 5) * M2 * 32;  // 32-column block of the table
+      char *dst = bbuf + (s % kRing) * kBBytes + wave * 2 * 1024;
 #pragma unroll
       for (int x = 0; x < 2; ++x)
-        __builtin_amdgcn_global_load_lds((const void *)(bsrc[x] + k),
+        __builtin_amdgcn_global_load_lds((const void *)(bsrc[x] + kofs),
                                          (__attribute__((address_space(3))) void *)(dst + x * 1024), 16, 0, 0);
-    };
-    auto copy_bits = [&](int s) {
       const int wi = min((kb + s * kKT) >> 5, W - 1);
-      __builtin_amdgcn_global_load_lds((const void *)(wsrc + wi),
-                                       (__attribute__((address_space(3))) void *)(wbuf + (s % kBitsBufs) * kBitsBytes +
+      __builtin_amdgcn_global_load_lds((const void *)(wsrc + (int64_t)wi * bits_rows),
+                                       (__attribute__((address_space(3))) void *)(wbuf + (s % kRing) * kBitsBytes +
                                                                                   wave * 256),
                                        4, 0, 0);
     };
-    // expand the 32 bits of row gr of stage s to packed BF16 (four 16-byte chunks)
-    auto store_mask = [&](int s) {
-      const uint32_t word = *(const uint32_t *)(wbuf + (s % kBitsBufs) * kBitsBytes + wslot);
-      const uint32_t b32 = (grow_ok && s < nst) ? word : 0u;
-      char *st = mbuf + (s & 1) * kMaskBytes + gr * kRowB;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        uint32_t w[4];
-#pragma unroll
-        for (int p2 = 0; p2 < 4; ++p2) {
-          const uint32_t t2 = b32 >> (8 * c + 2 * p2);
-          w[p2] = (t2 & 1u) * 0x3f80u + (t2 & 2u) * 0x1fc00000u;
-        }
-        lds_st16(st + ((c ^ gsw) << 4), u32x4{w[0], w[1], w[2], w[3]});
-      }
-    };
-    struct Frag {
-      bf16x8 a[4], h[2], l[2];
-    };
-    auto read_frag = [&](int s, int cofs, Frag &f) {
-      const char *ma = mbuf + (s & 1) * kMaskBytes + arow + cofs;
-      const char *mb = bbuf + (s % kBBufs) * kBBytes + brow + cofs;
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) f.a[rb] = __builtin_bit_cast(bf16x8, lds_ld16(ma + rb * 32 * kRowB));
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        f.h[cb] = __builtin_bit_cast(bf16x8, lds_ld16(mb + cb * 32 * kRowB));
-        f.l[cb] = __builtin_bit_cast(bf16x8, lds_ld16(mb + (kTC + cb * 32) * kRowB));
-      }
-    };
-    // 16 MFMAs of one K-step: 8 independent accumulators per operand plane
-    auto mma = [&](const Frag &f) {
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[rb], f.h[cb], acc[rb][cb], 0, 0, 0);
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[rb], f.l[cb], acc[rb][cb], 0, 0, 0);
-    };
-    // prologue: slabs 0, 1 and bit words 0..2 copied; stage 0's mask expanded
-    copy_slab(0);
-    copy_slab(1);
-    copy_bits(0);
-    copy_bits(1);
-    copy_bits(2);
-    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-    store_mask(0);
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    for (int s = 0; s < kAhead; ++s) copy_stage(s);
+    asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
     for (int s = 0; s < nst; ++s) {
-      copy_slab(s + 2);
-      copy_bits(s + 3);
-      Frag f0, f1;
-      read_frag(s, cks0, f0);
-      read_frag(s, cks1, f1);
-      mma(f0);
-      mma(f1);
-      store_mask(s + 1);
+      copy_stage(s + kAhead);
+      const char *sb = bbuf + (s % kRing) * kBBytes + brow;
+      const uint32_t *sw = (const uint32_t *)(wbuf + (s % kRing) * kBitsBytes) + wr * 128 + l32;
+      uint32_t word[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) word[rb] = (row_ok >> rb & 1u) ? sw[rb * 32] : 0u;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int cofs = ks ? cks1 : cks0;
+        bf16x8 bh[2], bl[2], a[4];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + cb * 32 * kRowB + cofs));
+          bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + (kTC + cb * 32) * kRowB + cofs));
+        }
+        // byte (2 ks + lhi) of the row word holds this lane's 8 columns of K-step ks
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) a[rb] = expand8((word[rb] >> (8 * (2 * ks + lhi))) & 0xffu);
+        // 8 independent accumulators per operand plane: consecutive MFMAs never wait on each other
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+      }
       stage_barrier();
     }
     // drain the copies still in flight before the work-group retires its LDS
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   // epilogue: register v of lane l holds row 8(v/4) + 4(l/32) + (v%4), column l%32
-  float *Ts = T + (int64_t)seg * seg_stride_f;
+  float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -367,21 +358,50 @@ int split_segments(const InstDev &d) { return (int)((d.Npad + kSplitSegLen - 1) 
 
 size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows) { return (size_t)chunk_rows * (size_t)(d.Npad / 32) * 4; }
 
+// K segments that intersect the disc chords of rows [row_begin, row_end).
+void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &seg_lo, int &seg_hi) {
+  const int64_t N = d.N;
+  int64_t rc = (N - 1) / 2;
+  if (rc < row_begin) rc = row_begin;
+  if (rc > row_end - 1) rc = row_end - 1;
+  int64_t best = -1;
+  for (int64_t r = rc; r <= rc + 1 && r < row_end; ++r) {
+    const int64_t c = 2 * r - N + 1;
+    const int64_t rem = (int64_t)d.kmax - c * c;
+    if (rem < 0) continue;
+    int64_t m = (int64_t)std::sqrt((double)rem);
+    while (m > 0 && m * m > rem) --m;
+    while ((m + 1) * (m + 1) <= rem) ++m;
+    if (m > best) best = m;
+  }
+  if (best < 0 || row_end <= row_begin) {
+    seg_lo = seg_hi = 0;
+    return;
+  }
+  const int64_t lo = (N - 1 - best + 1) / 2 > 0 ? (N - 1 - best + 1) / 2 : 0;
+  const int64_t hi = ((N - 1 + best) / 2 < N - 1 ? (N - 1 + best) / 2 : N - 1) + 1;
+  seg_lo = (int)(lo / kSplitSegLen);
+  seg_hi = (int)((hi - 1) / kSplitSegLen) + 1;
+}
+
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end, float2 *T,
                                  int64_t seg_stride, uint32_t *bits, hipStream_t st) {
   (void)S;
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
   const int W = (int)(d.Npad / 32);
+  int seg_lo, seg_hi;
+  split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
+  if (seg_hi <= seg_lo) return hipSuccess;
   {
-    const int64_t grid = rows < 65536 ? rows : 65536;
-    hipLaunchKernelGGL(k_mask_bits, dim3((unsigned)grid), dim3(256), 0, st, d, row_begin, row_end, W, bits);
+    const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)((W + 63) / 64));
+    hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, W, bits);
   }
   const int n_rt = (int)((rows + kTR - 1) / kTR);
   const int n_ct = (2 * d.M + kTC - 1) / kTC;
-  const int n_seg = split_segments(d);
+  const int n_seg = seg_hi - seg_lo;
   const int64_t G = (int64_t)n_rt * n_ct * n_seg;
-  const int64_t grid = (G + 7) / 8 * 8;
+  const int64_t grid = (G + 255) / 256 * 256;  // whole rounds of 8 XCDs x 32 slots
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e =
@@ -390,7 +410,7 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
     attr_set = true;
   }
   hipLaunchKernelGGL(k_row_pass_split, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, st, d, row_begin, row_end,
-                     n_rt, n_ct, n_seg, (const uint32_t *)bits, W, (float *)T, 2 * seg_stride);
+                     n_rt, n_ct, seg_lo, n_seg, (const uint32_t *)bits, W, rows, (float *)T, 2 * seg_stride);
   return hipGetLastError();
 }
 

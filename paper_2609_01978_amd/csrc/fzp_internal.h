@@ -103,6 +103,9 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
 int split_segments(const InstDev &d);
 constexpr int64_t kSplitSegLen = 65536;  // K columns per split-path segment
 size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows);  // zone-mask bit buffer of one chunk
+// K segments [seg_lo, seg_hi) holding disc samples of rows [row_begin, row_end);
+// the split row pass writes exactly these partials, the first at T.
+void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &seg_lo, int &seg_hi);
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
                                  float2 *T, int64_t seg_stride, uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,

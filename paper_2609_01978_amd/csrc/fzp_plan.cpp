@@ -430,7 +430,13 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
         if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
         (void)hipEventRecord(ea, st);
       }
-      const int nseg = split ? fzp::split_segments(ih.dev) : 1;
+      int nseg = 1;
+      if (split) {
+        int sl, sh;
+        fzp::split_seg_range(ih.dev, r0, r1, sl, sh);
+        nseg = sh - sl;
+        if (nseg <= 0) continue;  // no disc samples in these rows
+      }
       const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
       if (split)
         e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (uint32_t *)(ws + p.off_bits),
