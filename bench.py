@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the float64 comparison path")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=96, help="aperture rows in the CPU oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=256, help="aperture rows in the CPU oracle sample")
     return ap.parse_args()
 
 
@@ -44,6 +44,20 @@ def log(msg):
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+
+def bluestein_blocks(N: int, B: int) -> int:
+    """Blocks of B samples covering every aperture row's disc chord (row pass)."""
+    import numpy as np
+    c = 2 * np.arange(N, dtype=np.int64) - (N - 1)
+    rem = N * N - c * c
+    m = np.floor(np.sqrt(np.maximum(rem, 0).astype(np.float64))).astype(np.int64)
+    m -= (m * m > rem)
+    m += ((m + 1) * (m + 1) <= rem)
+    lo = (N - 1 - m + 1) // 2
+    hi = (N - 1 + m) // 2 + 1
+    length = np.where(rem >= 0, hi - lo, 0)
+    return int(np.sum((length + B - 1) // B))
 
 
 def cpu_baseline(w, rows_n: int):
@@ -124,19 +138,25 @@ def main():
     if fp64 is not None:
         rel = float(np.linalg.norm(split["I"] - fp64["I"]) / np.linalg.norm(fp64["I"]))
 
-    # roofline of the dominant kernel (split row pass): algorithmic flops per launch =
-    # 16 M flops per aperture sample (binary stripe, hi/lo operand: two real products of
-    # 2 real columns per complex ROI column) x the samples of the launch's rows.
+    # Roofline of the dominant kernel, the split row-pass GEMM (k_row_pass_split).
+    # Algorithmic work: the binary stripe times the hi/lo split kernel matrix is
+    # 2 real products (hi, lo) x 2 real MACs (re, im) per complex ROI column per
+    # aperture sample inside the disc = 8 M flops per disc sample.  The launch
+    # time comes from HIP events around each launch on the library's stream.
+    info = split["info"]
+    disc = float(info["disc_samples"])
     pr = split["prof"]
-    row_launch_ms = pr["row_ms"] / max(pr["row_launches"], 1)
     launches_per_step = pr["row_launches"] / max(args.steps, 1)
-    samples_per_launch = samples / max(launches_per_step, 1)
-    flops_per_launch = 16.0 * M * samples_per_launch
-    achieved = flops_per_launch / (row_launch_ms * 1e-3) / 1e12
-    roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+    row_ms_step = pr["row_ms"] / max(args.steps, 1)
+    flops_step = 8.0 * M * disc
+    achieved = flops_step / (row_ms_step * 1e-3) / 1e12
+    roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
-                    kernel="k_row_pass_split", launch_ms=round(row_launch_ms, 3),
-                    launches_per_step=launches_per_step)
+                    kernel="k_row_pass_split",
+                    launch_ms=round(pr["row_ms"] / max(pr["row_launches"], 1), 3),
+                    launches_per_step=launches_per_step,
+                    flops_per_launch=flops_step / max(launches_per_step, 1),
+                    work="8 M flops per aperture sample inside the disc (binary stripe, hi+lo BF16 products)")
 
     out = {
         "metric": "aperture Gsamples/s into ROI: split-BF16 MFMA vs FP64 Bluestein, rel-L2<=1e-4",
@@ -156,7 +176,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "split_bf16": {"gsamples_s": round(value, 3), "ms_per_step": round(split["ms"], 3),
-                       "row_pass_ms": round(pr["row_ms"] / max(args.steps, 1), 3),
+                       "row_pass_ms": round(row_ms_step, 3),
+                       "mask_bits_ms": round(pr["mask_ms"] / max(args.steps, 1), 3),
                        "col_pass_ms": round(pr["col_ms"] / max(args.steps, 1), 3),
                        "prepare_s": round(split["prep_s"], 3), "metrics": split["metrics"]},
         "valid_rel_l2_le_1e-4": (rel is not None and rel <= 1e-4),
@@ -164,12 +185,22 @@ def main():
     }
     if fp64 is not None:
         pf = fp64["prof"]
+        row_ms64 = pf["row_ms"] / max(args.fp64_steps, 1)
+        L, B = fp64["info"]["fft_len"], fp64["info"]["block"]
+        nblk = bluestein_blocks(N, B)
+        # algorithmic work per block: forward + inverse FFT of length L (5 L log2 L
+        # flops each) and the complex product with the filter spectrum (6 L)
+        flops64 = nblk * (2 * 5.0 * L * np.log2(L) + 6.0 * L)
+        ach64 = flops64 / (row_ms64 * 1e-3) / 1e12
         out["fp64_bluestein"] = {"gsamples_s": round(samples / (fp64["ms"] * 1e-3) / 1e9, 3),
                                  "ms_per_step": round(fp64["ms"], 3),
-                                 "row_pass_ms": round(pf["row_ms"] / max(args.fp64_steps, 1), 3),
+                                 "row_pass_ms": round(row_ms64, 3),
                                  "col_pass_ms": round(pf["col_ms"] / max(args.fp64_steps, 1), 3),
                                  "prepare_s": round(fp64["prep_s"], 3), "metrics": fp64["metrics"],
-                                 "fft_len": fp64["info"]["fft_len"], "block": fp64["info"]["block"]}
+                                 "fft_len": L, "block": B, "bluestein_blocks": int(nblk),
+                                 "roofline": dict(bound="alu", achieved=round(ach64, 2), peak=PEAK_FP64_TFLOPS,
+                                                  unit="TFLOP/s", frac=round(ach64 / PEAK_FP64_TFLOPS, 4),
+                                                  kernel="k_row_pass_fp64")}
         out["speedup_split_vs_fp64"] = round(fp64["ms"] / split["ms"], 3)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")

@@ -165,15 +165,16 @@ fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64
                            int32_t *stripe_rows, int32_t *path, int64_t *disc_samples,
                            double *kappa);
 
-/* Kernel timing.  While enabled, every row-pass and column-pass launch of
- * fzp_propagate_roi(_range) is bracketed by HIP events recorded on the
- * caller's stream, so each interval covers exactly that kernel.
+/* Kernel timing.  While enabled, every kernel launch of
+ * fzp_propagate_roi(_range) - row pass, column pass, and (split path) the
+ * zone-mask bit kernel - is bracketed by its own pair of HIP events recorded
+ * on the caller's stream, so each interval covers exactly that kernel.
  * fzp_profile_read waits for the recorded events and returns the accumulated
- * milliseconds and launch counts since the last reset (reset != 0 clears them).
- * Any output pointer may be NULL. */
+ * milliseconds and launch counts per kind since the last reset (reset != 0
+ * clears them).  Any output pointer may be NULL. */
 fzp_status_t fzp_profile_enable(fzp_plan_t p, int32_t on);
 fzp_status_t fzp_profile_read(fzp_plan_t p, double *row_ms, int64_t *row_launches, double *col_ms,
-                              int64_t *col_launches, int32_t reset);
+                              int64_t *col_launches, double *mask_ms, int64_t *mask_launches, int32_t reset);
 
 void fzp_destroy(fzp_plan_t p);
 

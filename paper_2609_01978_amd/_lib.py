@@ -111,6 +111,7 @@ def load_library() -> ctypes.CDLL:
     lib.fzp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.fzp_profile_enable.restype = st
     lib.fzp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     lib.fzp_profile_read.restype = st
     lib.fzp_destroy.argtypes = [P]
@@ -238,11 +239,13 @@ class Plan:
 
     def profile_read(self, reset: bool = True) -> dict:
         """Accumulated kernel milliseconds and launch counts (waits for the events)."""
-        rm, cm = ctypes.c_double(), ctypes.c_double()
-        rn, cn = ctypes.c_int64(), ctypes.c_int64()
+        rm, cm, am = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rn, cn, an = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self._lib, self._lib.fzp_profile_read(self._h, ctypes.byref(rm), ctypes.byref(rn), ctypes.byref(cm),
-                                                     ctypes.byref(cn), int(bool(reset))))
-        return dict(row_ms=rm.value, row_launches=rn.value, col_ms=cm.value, col_launches=cn.value)
+                                                     ctypes.byref(cn), ctypes.byref(am), ctypes.byref(an),
+                                                     int(bool(reset))))
+        return dict(row_ms=rm.value, row_launches=rn.value, col_ms=cm.value, col_launches=cn.value,
+                    mask_ms=am.value, mask_launches=an.value)
 
     def metrics(self, ws, roi, stream=None) -> list:
         out = (Metrics * self.n_instances)()

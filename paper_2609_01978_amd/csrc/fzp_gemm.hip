@@ -384,8 +384,17 @@ void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &
   seg_hi = (int)((hi - 1) / kSplitSegLen) + 1;
 }
 
+hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st) {
+  const int64_t rows = row_end - row_begin;
+  if (rows <= 0) return hipSuccess;
+  const int W = (int)(d.Npad / 32);
+  const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)((W + 63) / 64));
+  hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, W, bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end, float2 *T,
-                                 int64_t seg_stride, uint32_t *bits, hipStream_t st) {
+                                 int64_t seg_stride, const uint32_t *bits, hipStream_t st) {
   (void)S;
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
@@ -393,10 +402,6 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   int seg_lo, seg_hi;
   split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
   if (seg_hi <= seg_lo) return hipSuccess;
-  {
-    const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)((W + 63) / 64));
-    hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, W, bits);
-  }
   const int n_rt = (int)((rows + kTR - 1) / kTR);
   const int n_ct = (2 * d.M + kTC - 1) / kTC;
   const int n_seg = seg_hi - seg_lo;
@@ -410,7 +415,7 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
     attr_set = true;
   }
   hipLaunchKernelGGL(k_row_pass_split, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, st, d, row_begin, row_end,
-                     n_rt, n_ct, seg_lo, n_seg, (const uint32_t *)bits, W, rows, (float *)T, 2 * seg_stride);
+                     n_rt, n_ct, seg_lo, n_seg, bits, W, rows, (float *)T, 2 * seg_stride);
   return hipGetLastError();
 }
 

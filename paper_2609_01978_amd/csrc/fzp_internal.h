@@ -86,9 +86,9 @@ struct Plan {
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<size_t, int>> ev_marks;  // (first event index, 0 = row / 1 = column)
-  double row_ms = 0.0, col_ms = 0.0;
-  int64_t row_n = 0, col_n = 0;
+  std::vector<std::pair<size_t, int>> ev_marks;  // (first event index, 0 = row / 1 = column / 2 = mask bits)
+  double row_ms = 0.0, col_ms = 0.0, aux_ms = 0.0;
+  int64_t row_n = 0, col_n = 0, aux_n = 0;
   ~Plan();
 };
 
@@ -106,8 +106,9 @@ size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows);  // zone-mask bit
 // K segments [seg_lo, seg_hi) holding disc samples of rows [row_begin, row_end);
 // the split row pass writes exactly these partials, the first at T.
 void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &seg_lo, int &seg_hi);
+hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st);
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
-                                 float2 *T, int64_t seg_stride, uint32_t *bits, hipStream_t st);
+                                 float2 *T, int64_t seg_stride, const uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,
                            bool t_is_fp32, int nseg, int64_t seg_stride, double2 *roi, hipStream_t st);
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,

@@ -423,13 +423,6 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
       const int64_t r0 = c0 > row_begin ? c0 : row_begin;
       const int64_t r1 = c0 + p.chunk_rows < row_end ? c0 + p.chunk_rows : row_end;
       if (r1 <= r0) continue;
-      hipEvent_t ea = nullptr, eb = nullptr;
-      size_t first = 0;
-      if (p.profile) {
-        e = take_events(p, ea, eb, first);
-        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-        (void)hipEventRecord(ea, st);
-      }
       int nseg = 1;
       if (split) {
         int sl, sh;
@@ -438,25 +431,41 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
         if (nseg <= 0) continue;  // no disc samples in these rows
       }
       const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
+      hipEvent_t ea = nullptr, eb = nullptr;
+      size_t first = 0;
+      // each launch is bracketed by its own pair of events when profiling
+      auto begin_mark = [&]() -> hipError_t {
+        if (!p.profile) return hipSuccess;
+        hipError_t pe = take_events(p, ea, eb, first);
+        if (pe == hipSuccess) pe = hipEventRecord(ea, st);
+        return pe;
+      };
+      auto end_mark = [&](int kind) -> hipError_t {
+        if (!p.profile) return hipSuccess;
+        hipError_t pe = hipEventRecord(eb, st);
+        p.ev_marks.emplace_back(first, kind);
+        return pe;
+      };
+      if (split) {
+        e = begin_mark();
+        if (e == hipSuccess) e = fzp::launch_mask_bits(ih.dev, r0, r1, (uint32_t *)(ws + p.off_bits), st);
+        if (e == hipSuccess) e = end_mark(2);
+        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: mask bits", e);
+      }
+      e = begin_mark();
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
       if (split)
-        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (uint32_t *)(ws + p.off_bits),
+        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (const uint32_t *)(ws + p.off_bits),
                                        st);
       else
         e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
-      if (p.profile) {
-        (void)hipEventRecord(eb, st);
-        p.ev_marks.emplace_back(first, 0);
-        e = take_events(p, ea, eb, first);
-        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-        (void)hipEventRecord(ea, st);
-      }
+      e = end_mark(0);
+      if (e == hipSuccess) e = begin_mark();
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
       e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, nseg, seg_stride, roi, st);
+      if (e == hipSuccess) e = end_mark(1);
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
-      if (p.profile) {
-        (void)hipEventRecord(eb, st);
-        p.ev_marks.emplace_back(first, 1);
-      }
     }
   }
   return FZP_OK;
@@ -499,7 +508,8 @@ extern "C" fzp_status_t fzp_profile_enable(fzp_plan_t h, int32_t on) {
 }
 
 extern "C" fzp_status_t fzp_profile_read(fzp_plan_t h, double *row_ms, int64_t *row_launches, double *col_ms,
-                                         int64_t *col_launches, int32_t reset) {
+                                         int64_t *col_launches, double *aux_ms, int64_t *aux_launches,
+                                         int32_t reset) {
   if (!h) return fail(FZP_E_INVAL, "fzp_profile_read: NULL plan");
   Plan &p = h->plan;
   for (const auto &mk : p.ev_marks) {
@@ -511,9 +521,12 @@ extern "C" fzp_status_t fzp_profile_read(fzp_plan_t h, double *row_ms, int64_t *
     if (mk.second == 0) {
       p.row_ms += ms;
       ++p.row_n;
-    } else {
+    } else if (mk.second == 1) {
       p.col_ms += ms;
       ++p.col_n;
+    } else {
+      p.aux_ms += ms;
+      ++p.aux_n;
     }
   }
   p.ev_marks.clear();
@@ -522,9 +535,11 @@ extern "C" fzp_status_t fzp_profile_read(fzp_plan_t h, double *row_ms, int64_t *
   if (row_launches) *row_launches = p.row_n;
   if (col_ms) *col_ms = p.col_ms;
   if (col_launches) *col_launches = p.col_n;
+  if (aux_ms) *aux_ms = p.aux_ms;
+  if (aux_launches) *aux_launches = p.aux_n;
   if (reset) {
-    p.row_ms = p.col_ms = 0.0;
-    p.row_n = p.col_n = 0;
+    p.row_ms = p.col_ms = p.aux_ms = 0.0;
+    p.row_n = p.col_n = p.aux_n = 0;
   }
   return FZP_OK;
 }
