@@ -354,3 +354,26 @@ def test_v8_grid_rule(row):
         dx, n = O.v8_grid(D, f, 532e-9, L)
     assert n == nx
     assert abs(dx * 1e6 - dx_um) <= 0.0006
+
+
+# --------------------------------------------------------------------------
+# Deformation model: straight Gaussian ridges, width given as the FWHM
+# --------------------------------------------------------------------------
+
+def test_crease_height_profile():
+    """h = H at the ridge line, H/2 at a distance of half the width (FWHM),
+    H/16 at a full width, and the ridge runs along theta + pi/2."""
+    H, w, th, rho = 3e-7, 1.2e-3, 0.4, 2e-4
+    cr = np.array([[th, rho, w, H]])
+    n = np.array([math.cos(th), math.sin(th)])
+    t = np.array([-math.sin(th), math.cos(th)])
+    for s in (-2e-3, 0.0, 5e-4):              # any point along the ridge
+        p0 = rho * n + s * t
+        for d, want in ((0.0, H), (0.5 * w, 0.5 * H), (-0.5 * w, 0.5 * H), (w, H / 16)):
+            p = p0 + d * n
+            assert abs(float(O.crease_height(p[0], p[1], cr)) - want) <= 1e-12 * H
+    # ridges add
+    cr2 = np.array([[th, rho, w, H], [th + 1.0, -rho, 2 * w, 0.5 * H]])
+    x, y = 1.3e-4, -7e-4
+    assert abs(float(O.crease_height(x, y, cr2)) - float(O.crease_height(x, y, cr2[:1]))
+               - float(O.crease_height(x, y, cr2[1:]))) < 1e-20
