@@ -53,6 +53,7 @@ struct InstDev {
   const CreaseDev *cr;
   const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
   int64_t Npad;
+  int64_t seg_len;         // split path: K columns per float32 partial sum (power of two)
 };
 
 struct InstHost {
@@ -79,6 +80,7 @@ struct Plan {
   int64_t roi_elems;
   size_t off_T, T_bytes;
   size_t off_bits = 0, bits_bytes = 0;
+  size_t off_G = 0, G_bytes = 0;  // split path, deformed stripes
   size_t off_scratch, scratch_bytes;
   size_t ws_bytes;
   const void *prepared_ws = nullptr;
@@ -101,12 +103,18 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
 // Split row pass: writes split_segments(d) partial results, each chunk_rows x M
 // complex float32, seg_stride complex elements apart.
 int split_segments(const InstDev &d);
-constexpr int64_t kSplitSegLen = 65536;  // K columns per split-path segment
 size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows);  // zone-mask bit buffer of one chunk
 // K segments [seg_lo, seg_hi) holding disc samples of rows [row_begin, row_end);
 // the split row pass writes exactly these partials, the first at T.
 void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &seg_lo, int &seg_hi);
 hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st);
+// Deformed (complex) stripes on the split path: the BF16 hi/lo stripe planes of
+// one chunk (split_stripe_bytes for chunk_rows rows), then the complex GEMM.
+void split_chunk_chord(const InstDev &d, int64_t row_begin, int64_t row_end, int64_t &lo, int64_t &hi);
+size_t split_stripe_bytes(const InstDev &d, int64_t chunk_rows);
+hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, uint16_t *G, hipStream_t st);
+hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T,
+                                      int64_t seg_stride, const uint16_t *G, hipStream_t st);
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
                                  float2 *T, int64_t seg_stride, const uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,

@@ -205,19 +205,23 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       delete h;
       return fail(FZP_E_INVAL, "fzp_plan: split path stripe_rows must be 64, 128 or 256");
     }
+    bool cplx = false;  // split path with deformed (complex) stripes
     if (split)
-      for (const auto &ih : p.inst)
-        if (ih.in.n_creases > 0) {
-          delete h;
-          return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path does not take creases yet");
-        }
+      for (const auto &ih : p.inst) cplx = cplx || ih.in.n_creases > 0;
     if (split)
       for (const auto &ih : p.inst)
         if (ih.in.M % 16 != 0) {
           delete h;
           return fail(FZP_E_UNSUPPORTED, "fzp_plan: the split path needs M to be a multiple of 16");
         }
-    const int64_t nseg = split ? (N + fzp::kSplitSegLen - 1) / fzp::kSplitSegLen : 1;
+    // split path: K is cut into segments of seg_len columns, each summed in
+    // float32 and the segments added in float64 by the column pass; about 8
+    // segments per row (4096 .. 65536 columns) also gives the GEMM grid
+    // enough independent tiles at small N
+    int64_t seg_len = 4096;
+    while (seg_len < 65536 && seg_len * 16 <= N) seg_len *= 2;
+    for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
+    const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
     const size_t tbytes = split ? sizeof(float) * 2 * (size_t)nseg : sizeof(double) * 2;
     if (o.chunk_rows > 0) {
       p.chunk_rows = o.chunk_rows;
@@ -227,6 +231,13 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       c = c / p.S * p.S;
       if (c < p.S) c = p.S;
       p.chunk_rows = c < N ? c : N;
+    }
+    if (split && cplx && o.chunk_rows <= 0) {
+      // the complex stripe planes (8 bytes per sample of a chunk) stay near 2 GiB
+      const int64_t npad = (N + 63) / 64 * 64;
+      int64_t c = (int64_t)(((size_t)2 << 30) / ((size_t)npad * 8)) / 256 * 256;
+      if (c < 256) c = 256;
+      if (c < p.chunk_rows) p.chunk_rows = c;
     }
     if (split) p.chunk_rows = (p.chunk_rows + p.S - 1) / p.S * p.S;
 
@@ -277,6 +288,11 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       p.off_bits = off;
       p.bits_bytes = align256(fzp::split_bits_bytes(p.inst[0].dev, p.chunk_rows));
       off += p.bits_bytes;
+      if (cplx) {
+        p.off_G = off;
+        p.G_bytes = align256(fzp::split_stripe_bytes(p.inst[0].dev, p.chunk_rows));
+        off += p.G_bytes;
+      }
     }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
@@ -446,15 +462,22 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
         p.ev_marks.emplace_back(first, kind);
         return pe;
       };
+      const bool cplx = split && ih.dev.n_creases > 0;
       if (split) {
+        // the stripe operand: zone-mask bits, or the complex BF16 stripe planes
         e = begin_mark();
-        if (e == hipSuccess) e = fzp::launch_mask_bits(ih.dev, r0, r1, (uint32_t *)(ws + p.off_bits), st);
+        if (e == hipSuccess)
+          e = cplx ? fzp::launch_stripe_cplx(ih.dev, r0, r1, (uint16_t *)(ws + p.off_G), st)
+                   : fzp::launch_mask_bits(ih.dev, r0, r1, (uint32_t *)(ws + p.off_bits), st);
         if (e == hipSuccess) e = end_mark(2);
-        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: mask bits", e);
+        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
       }
       e = begin_mark();
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-      if (split)
+      if (cplx)
+        e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride, (const uint16_t *)(ws + p.off_G),
+                                            st);
+      else if (split)
         e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (const uint32_t *)(ws + p.off_bits),
                                        st);
       else
