@@ -31,6 +31,7 @@ __all__ = [
     "batch_wavelengths",
     "batch_roi_sizes",
     "surrogate_draws",
+    "batch64_instances",
 ]
 
 LAMBDA0 = 632.8e-9
@@ -91,3 +92,19 @@ def surrogate_draws(seed: int, n: int, D: float, lambda0: float, n_creases: int 
     height = rng.uniform(0.0, 0.5 * lambda0, (n, n_creases))
     lam = rng.uniform(lambda_lo, lambda_hi, n)
     return np.stack([theta, offset, width, height], axis=2), lam
+
+
+def batch64_instances(w: dict = None) -> list:
+    """The 64 instances of the batch workload: instance k = 16 m + l takes crease
+    map m (seeded ``map_seeds[m]``), wavelength l of ``batch_wavelengths`` and the
+    k-th seeded ROI size; each sits at its first-order focus (z = 0)."""
+    w = WORKLOADS["batch64"] if w is None else w
+    lams = batch_wavelengths(w["n_lambda"])
+    Ms = batch_roi_sizes(w["m_seed"], w["n_lambda"] * w["n_maps"], w["m_choices"])
+    out = []
+    for m in range(w["n_maps"]):
+        cr = crease_draws(w["map_seeds"][m], w["D"], w["lambda0"], w["n_creases"])
+        for li in range(w["n_lambda"]):
+            k = m * w["n_lambda"] + li
+            out.append(dict(lam=float(lams[li]), M=int(Ms[k]), creases=cr))
+    return out

@@ -103,7 +103,9 @@ typedef struct {
   uint64_t workspace_limit; /* bytes; 0 = no limit.  fzp_plan fails with FZP_E_NOMEM
                                if the workspace would exceed it */
   int32_t flags;        /* FZP_FLAG_* */
-  int32_t reserved;
+  int32_t lanes;        /* instances propagated concurrently, each lane on its own
+                           internal stream with its own stripe buffers (the workspace
+                           grows by one set of stripe buffers per lane); 0 = 1, at most 8 */
 } fzp_options_t;
 
 /* Main-lobe metrics of one instance (shared metric extractor, Sec. 3.3 stage 4
@@ -175,6 +177,33 @@ fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64
 fzp_status_t fzp_profile_enable(fzp_plan_t p, int32_t on);
 fzp_status_t fzp_profile_read(fzp_plan_t p, double *row_ms, int64_t *row_launches, double *col_ms,
                               int64_t *col_launches, double *mask_ms, int64_t *mask_launches, int32_t reset);
+
+/* Batched execution.  fzp_graph_create records one whole fzp_propagate_roi of
+ * the plan (every instance, every chunk, all lanes forked from and joined back
+ * to one stream) into a HIP graph bound to `workspace` and `roi_dev`, which
+ * must stay allocated while the graph lives; fzp_graph_launch replays it on
+ * `stream` as one launch.  The workspace is prepared first (synchronously).
+ * Kernel timing (fzp_profile_*) is not recorded inside a graph.  Errors:
+ * FZP_E_INVAL, FZP_E_DEVICE. */
+typedef struct fzp_graph_s *fzp_graph_t;
+fzp_status_t fzp_graph_create(fzp_plan_t p, void *workspace, double *roi_dev, fzp_graph_t *out);
+fzp_status_t fzp_graph_launch(fzp_graph_t g, void *stream);
+void fzp_graph_destroy(fzp_graph_t g);
+
+/* Autotuner of the split path's GEMM work decomposition.  Candidates are the
+ * K-segment length of a work-group tile (the plan's default and its doublings
+ * up to 65536 columns; longer segments mean fewer float32 partial planes for
+ * the column pass but fewer independent tiles) and the number of concurrent
+ * lanes (1 .. options.lanes).  Each candidate runs one full propagation on
+ * `stream`, timed with HIP events; the fastest is kept in the plan.  With a
+ * non-NULL `cache_path` the choice is looked up first in that text file (one
+ * "key seg_len lanes" line per plan shape and GPU) and appended when new.
+ * `roi_dev` is overwritten.  seg_len_out / lanes_out / ms_out (the winning
+ * time, 0 when taken from the cache) may be NULL.  The FP64 path has nothing
+ * to tune except lanes.  Errors: FZP_E_INVAL, FZP_E_DEVICE. */
+fzp_status_t fzp_autotune(fzp_plan_t p, void *workspace, double *roi_dev, void *stream,
+                          const char *cache_path, int64_t *seg_len_out, int32_t *lanes_out,
+                          double *ms_out);
 
 void fzp_destroy(fzp_plan_t p);
 

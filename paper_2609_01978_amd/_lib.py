@@ -33,7 +33,8 @@ FLAG_ALLOW_UNDERSAMPLED = 1
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
     "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
-    "fzp_last_error", "fzp_profile_enable", "fzp_profile_read",
+    "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
+    "fzp_graph_destroy", "fzp_autotune",
 ]
 
 
@@ -62,7 +63,7 @@ class Instance(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("stripe_rows", ctypes.c_int32), ("chunk_rows", ctypes.c_int64),
-                ("workspace_limit", ctypes.c_uint64), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("workspace_limit", ctypes.c_uint64), ("flags", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 class Metrics(ctypes.Structure):
@@ -114,6 +115,15 @@ def load_library() -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     lib.fzp_profile_read.restype = st
+    lib.fzp_graph_create.argtypes = [P, P, P, ctypes.POINTER(P)]
+    lib.fzp_graph_create.restype = st
+    lib.fzp_graph_launch.argtypes = [P, P]
+    lib.fzp_graph_launch.restype = st
+    lib.fzp_graph_destroy.argtypes = [P]
+    lib.fzp_graph_destroy.restype = None
+    lib.fzp_autotune.argtypes = [P, P, P, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.fzp_autotune.restype = st
     lib.fzp_destroy.argtypes = [P]
     lib.fzp_destroy.restype = None
     lib.fzp_last_error.argtypes = []
@@ -144,7 +154,8 @@ class Plan:
     """A propagation plan: an aperture and one or more instances (lambda, z, ROI, creases)."""
 
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
-                 chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False):
+                 chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
+                 lanes: int = 0):
         lib = load_library()
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
@@ -165,7 +176,7 @@ class Plan:
                               n_creases=ncr, creases=ctypes.cast(cbuf, ctypes.POINTER(Crease)))
         p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16}[path] if isinstance(path, str) else int(path)
         opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
-                      flags=FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0, reserved=0)
+                      flags=FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0, lanes=int(lanes))
         h = ctypes.c_void_p()
         _check(lib, lib.fzp_plan(ctypes.byref(ap), arr, n, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -251,3 +262,35 @@ class Plan:
         out = (Metrics * self.n_instances)()
         _check(self._lib, self._lib.fzp_metrics(self._h, _ptr(ws), _ptr(roi), out, _stream_handle(stream)))
         return [out[k].as_dict() for k in range(self.n_instances)]
+
+    def autotune(self, ws, roi, cache_path: Optional[str] = None, stream=None) -> dict:
+        """Pick the split GEMM's K-segment length and the lane count by timing (overwrites roi)."""
+        sl, ln, ms = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib, self._lib.fzp_autotune(self._h, _ptr(ws), _ptr(roi), _stream_handle(stream), cp,
+                                                 ctypes.byref(sl), ctypes.byref(ln), ctypes.byref(ms)))
+        return dict(seg_len=sl.value, lanes=ln.value, ms=ms.value)
+
+    def graph(self, ws, roi) -> "Graph":
+        """One whole propagation of the plan captured as a HIP graph bound to ws and roi."""
+        return Graph(self, ws, roi)
+
+
+class Graph:
+    """A captured propagation (fzp_graph_create); keeps its plan and buffers alive."""
+
+    def __init__(self, plan: Plan, ws, roi):
+        self._lib = plan._lib
+        self._keep = (plan, ws, roi)
+        g = ctypes.c_void_p()
+        _check(self._lib, self._lib.fzp_graph_create(plan._h, _ptr(ws), _ptr(roi), ctypes.byref(g)))
+        self._g = g
+
+    def launch(self, stream=None):
+        _check(self._lib, self._lib.fzp_graph_launch(self._g, _stream_handle(stream)))
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            self._lib.fzp_graph_destroy(g)
+            self._g = None

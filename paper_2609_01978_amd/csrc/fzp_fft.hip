@@ -219,7 +219,12 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   const int t = threadIdx.x;
   const Tw tw = fft_twiddles();
   const int M = d.M;
-  for (int q = blockIdx.x; q < M; q += gridDim.x) {
+  // Work-groups are dealt to the 8 XCDs round robin; with one work-group per
+  // column, XCD x takes the contiguous columns [x M/8, (x+1) M/8), so the
+  // work-groups sharing an XCD's L2 read adjacent elements of each T row.
+  int q0 = blockIdx.x;
+  if (gridDim.x == (unsigned)M && (M & 7) == 0) q0 = (q0 & 7) * (M >> 3) + (q0 >> 3);
+  for (int q = q0; q < M; q += gridDim.x) {
     double2 acc[NQ];
     bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, [&](int64_t j) -> double2 {
       const TT *src = T + (j - row_begin) * (int64_t)M + q;

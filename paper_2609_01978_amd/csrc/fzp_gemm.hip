@@ -600,6 +600,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, 
 
 }  // namespace
 
+hipError_t init_split_attributes() {
+  static bool done = false;  // set once per process (the attributes are per function)
+  if (done) return hipSuccess;
+  hipError_t e =
+      hipFuncSetAttribute((const void *)k_row_pass_split, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kCLdsBytes);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
 hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws, hipStream_t st) {
   (void)p;
   InstDev d = ih.dev;
@@ -672,13 +684,8 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   const int n_seg = seg_hi - seg_lo;
   const int64_t G = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (G + 255) / 256 * 256;  // whole rounds of 8 XCDs x 32 slots
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_row_pass_split, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = init_split_attributes();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_pass_split, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, st, d, row_begin, row_end,
                      n_rt, n_ct, seg_lo, n_seg, bits, W, rows, (float *)T, 2 * seg_stride);
   return hipGetLastError();
@@ -725,13 +732,8 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
   const int n_seg = seg_hi - seg_lo;
   const int64_t Gn = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (Gn + 255) / 256 * 256;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kCLdsBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = init_split_attributes();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_pass_split_cplx, dim3((unsigned)grid), dim3(kThreads), kCLdsBytes, st, d, row_begin,
                      row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride);
   return hipGetLastError();

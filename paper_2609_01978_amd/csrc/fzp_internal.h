@@ -78,9 +78,14 @@ struct Plan {
   int32_t Mmax;
   std::vector<InstHost> inst;
   int64_t roi_elems;
-  size_t off_T, T_bytes;
-  size_t off_bits = 0, bits_bytes = 0;
-  size_t off_G = 0, G_bytes = 0;  // split path, deformed stripes
+  // stripe buffers, one set per lane: row-pass result T, zone-mask bits and
+  // complex stripe planes (split path)
+  size_t T_bytes = 0, bits_bytes = 0, G_bytes = 0;
+  std::vector<size_t> off_T, off_bits, off_G;
+  int32_t lanes_max = 1, lanes = 1;
+  int64_t seg_len = 0;  // split path K segment (all instances)
+  std::vector<hipStream_t> lane_st;
+  std::vector<hipEvent_t> lane_ev;  // [0] fork, [1 + l] join of lane l
   size_t off_scratch, scratch_bytes;
   size_t ws_bytes;
   const void *prepared_ws = nullptr;
@@ -97,6 +102,7 @@ struct Plan {
 // ---- launchers (fzp_fft.hip, fzp_gemm.hip, fzp_metrics.hip) ----
 hipError_t launch_build_tables(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
 hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
+hipError_t init_split_attributes();  // kernel attributes of the split GEMMs (outside graph capture)
 hipError_t launch_zero(double *buf, int64_t n_doubles, hipStream_t st);
 hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row_end, double2 *T,
                                 hipStream_t st);

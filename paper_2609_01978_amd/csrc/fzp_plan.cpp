@@ -2,9 +2,14 @@
 // parameters of each instance (Sec. 3.3 stage 1, Eq. 10; Fig. 18 stage 1),
 // the workspace layout and the stripe/chunk schedule of a propagation.
 
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <exception>
+#include <fstream>
+#include <sstream>
 #include <limits>
 #include <new>
 #include <string>
@@ -58,6 +63,8 @@ struct fzp_plan_s {
 
 fzp::Plan::~Plan() {
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : lane_ev) (void)hipEventDestroy(e);
+  for (hipStream_t t : lane_st) (void)hipStreamDestroy(t);
 }
 
 namespace {
@@ -100,6 +107,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     if (ap->N < 1 || ap->N > (int64_t(1) << 21)) return fail(FZP_E_INVAL, "fzp_plan: N must be in 1 .. 2^21");
     if (ap->centre_open != 0 && ap->centre_open != 1) return fail(FZP_E_INVAL, "fzp_plan: centre_open must be 0 or 1");
     if (o.stripe_rows < 0 || o.chunk_rows < 0) return fail(FZP_E_INVAL, "fzp_plan: negative stripe or chunk rows");
+    if (o.lanes < 0 || o.lanes > 8) return fail(FZP_E_INVAL, "fzp_plan: lanes must be in 0 .. 8");
 
     auto h = new (std::nothrow) fzp_plan_s;
     if (!h) return fail(FZP_E_NOMEM, "fzp_plan: out of host memory");
@@ -220,7 +228,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     // enough independent tiles at small N
     int64_t seg_len = 4096;
     while (seg_len < 65536 && seg_len * 16 <= N) seg_len *= 2;
+    p.seg_len = seg_len;
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
+    p.lanes_max = o.lanes > 0 ? o.lanes : 1;
+    p.lanes = p.lanes_max;
     const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
     const size_t tbytes = split ? sizeof(float) * 2 * (size_t)nseg : sizeof(double) * 2;
     if (o.chunk_rows > 0) {
@@ -281,18 +292,18 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         ih.dev.Npad = npad;
       }
     }
-    p.off_T = off;
     p.T_bytes = align256((size_t)p.chunk_rows * p.Mmax * tbytes);
-    off += p.T_bytes;
     if (split) {
-      p.off_bits = off;
       p.bits_bytes = align256(fzp::split_bits_bytes(p.inst[0].dev, p.chunk_rows));
+      if (cplx) p.G_bytes = align256(fzp::split_stripe_bytes(p.inst[0].dev, p.chunk_rows));
+    }
+    for (int l = 0; l < p.lanes_max; ++l) {
+      p.off_T.push_back(off);
+      off += p.T_bytes;
+      p.off_bits.push_back(off);
       off += p.bits_bytes;
-      if (cplx) {
-        p.off_G = off;
-        p.G_bytes = align256(fzp::split_stripe_bytes(p.inst[0].dev, p.chunk_rows));
-        off += p.G_bytes;
-      }
+      p.off_G.push_back(off);
+      off += p.G_bytes;
     }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
@@ -403,6 +414,10 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
         if (e != hipSuccess) return hip_fail("fzp_prepare: split table kernel", e);
       }
     }
+    if (p.opt.path == FZP_PATH_SPLIT_BF16) {
+      hipError_t e = fzp::init_split_attributes();
+      if (e != hipSuccess) return hip_fail("fzp_prepare: kernel attributes", e);
+    }
     p.prepared_ws = workspace;
     return FZP_OK;
   } catch (const std::exception &e) {
@@ -411,6 +426,94 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
     return fail(FZP_E_INVAL, "fzp_prepare: unknown error");
   }
 }
+
+namespace {
+
+// Internal lane streams and their fork/join events (created on first use).
+hipError_t ensure_lanes(Plan &p) {
+  if (p.lanes <= 1 || (int)p.lane_st.size() >= p.lanes_max) return hipSuccess;
+  while ((int)p.lane_st.size() < p.lanes_max) {
+    hipStream_t t;
+    hipError_t e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    p.lane_st.push_back(t);
+  }
+  while ((int)p.lane_ev.size() < p.lanes_max + 1) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    p.lane_ev.push_back(ev);
+  }
+  return hipSuccess;
+}
+
+// Rows [row_begin, row_end) of instance ih into its ROI, on stream st with the
+// stripe buffers of `lane`.
+fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2 *roi, int64_t row_begin,
+                              int64_t row_end, hipStream_t st) {
+  const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
+  const bool cplx = split && ih.dev.n_creases > 0;
+  void *T = ws + p.off_T[lane];
+  uint32_t *bits = (uint32_t *)(ws + p.off_bits[lane]);
+  uint16_t *G = (uint16_t *)(ws + p.off_G[lane]);
+  hipError_t e;
+  // chunks are aligned to multiples of chunk_rows from row 0
+  int64_t c0 = row_begin / p.chunk_rows * p.chunk_rows;
+  for (; c0 < row_end; c0 += p.chunk_rows) {
+    const int64_t r0 = c0 > row_begin ? c0 : row_begin;
+    const int64_t r1 = c0 + p.chunk_rows < row_end ? c0 + p.chunk_rows : row_end;
+    if (r1 <= r0) continue;
+    int nseg = 1;
+    if (split) {
+      int sl, sh;
+      fzp::split_seg_range(ih.dev, r0, r1, sl, sh);
+      nseg = sh - sl;
+      if (nseg <= 0) continue;  // no disc samples in these rows
+    }
+    const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    size_t first = 0;
+    // each launch is bracketed by its own pair of events when profiling
+    auto begin_mark = [&]() -> hipError_t {
+      if (!p.profile) return hipSuccess;
+      hipError_t pe = take_events(p, ea, eb, first);
+      if (pe == hipSuccess) pe = hipEventRecord(ea, st);
+      return pe;
+    };
+    auto end_mark = [&](int kind) -> hipError_t {
+      if (!p.profile) return hipSuccess;
+      hipError_t pe = hipEventRecord(eb, st);
+      p.ev_marks.emplace_back(first, kind);
+      return pe;
+    };
+    if (split) {
+      // the stripe operand: zone-mask bits, or the complex BF16 stripe planes
+      e = begin_mark();
+      if (e == hipSuccess)
+        e = cplx ? fzp::launch_stripe_cplx(ih.dev, r0, r1, G, st) : fzp::launch_mask_bits(ih.dev, r0, r1, bits, st);
+      if (e == hipSuccess) e = end_mark(2);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
+    }
+    e = begin_mark();
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
+    if (cplx)
+      e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride, G, st);
+    else if (split)
+      e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, bits, st);
+    else
+      e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
+    e = end_mark(0);
+    if (e == hipSuccess) e = begin_mark();
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
+    e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, nseg, seg_stride, roi, st);
+    if (e == hipSuccess) e = end_mark(1);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
+  }
+  return FZP_OK;
+}
+
+}  // namespace
 
 extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, double *roi_dev, int64_t row_begin,
                                                 int64_t row_end, int32_t accumulate, void *stream) {
@@ -429,68 +532,34 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
     e = fzp::launch_zero(roi_dev, 2 * p.roi_elems, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: zero", e);
   }
-  const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
-  void *T = ws + p.off_T;
-  for (auto &ih : p.inst) {
-    double2 *roi = (double2 *)roi_dev + ih.roi_off;
-    // chunks are aligned to multiples of chunk_rows from row 0
-    int64_t c0 = row_begin / p.chunk_rows * p.chunk_rows;
-    for (; c0 < row_end; c0 += p.chunk_rows) {
-      const int64_t r0 = c0 > row_begin ? c0 : row_begin;
-      const int64_t r1 = c0 + p.chunk_rows < row_end ? c0 + p.chunk_rows : row_end;
-      if (r1 <= r0) continue;
-      int nseg = 1;
-      if (split) {
-        int sl, sh;
-        fzp::split_seg_range(ih.dev, r0, r1, sl, sh);
-        nseg = sh - sl;
-        if (nseg <= 0) continue;  // no disc samples in these rows
-      }
-      const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
-      hipEvent_t ea = nullptr, eb = nullptr;
-      size_t first = 0;
-      // each launch is bracketed by its own pair of events when profiling
-      auto begin_mark = [&]() -> hipError_t {
-        if (!p.profile) return hipSuccess;
-        hipError_t pe = take_events(p, ea, eb, first);
-        if (pe == hipSuccess) pe = hipEventRecord(ea, st);
-        return pe;
-      };
-      auto end_mark = [&](int kind) -> hipError_t {
-        if (!p.profile) return hipSuccess;
-        hipError_t pe = hipEventRecord(eb, st);
-        p.ev_marks.emplace_back(first, kind);
-        return pe;
-      };
-      const bool cplx = split && ih.dev.n_creases > 0;
-      if (split) {
-        // the stripe operand: zone-mask bits, or the complex BF16 stripe planes
-        e = begin_mark();
-        if (e == hipSuccess)
-          e = cplx ? fzp::launch_stripe_cplx(ih.dev, r0, r1, (uint16_t *)(ws + p.off_G), st)
-                   : fzp::launch_mask_bits(ih.dev, r0, r1, (uint32_t *)(ws + p.off_bits), st);
-        if (e == hipSuccess) e = end_mark(2);
-        if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
-      }
-      e = begin_mark();
-      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-      if (cplx)
-        e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride, (const uint16_t *)(ws + p.off_G),
-                                            st);
-      else if (split)
-        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, (const uint32_t *)(ws + p.off_bits),
-                                       st);
-      else
-        e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
-      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
-      e = end_mark(0);
-      if (e == hipSuccess) e = begin_mark();
-      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-      e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, nseg, seg_stride, roi, st);
-      if (e == hipSuccess) e = end_mark(1);
-      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
+  const int lanes = p.lanes < (int)p.inst.size() ? p.lanes : (int)p.inst.size();
+  if (lanes <= 1) {
+    for (auto &ih : p.inst) {
+      const fzp_status_t s =
+          enqueue_instance(p, ih, 0, ws, (double2 *)roi_dev + ih.roi_off, row_begin, row_end, st);
+      if (s != FZP_OK) return s;
     }
+    return FZP_OK;
   }
+  // fork: every lane stream waits for the work already on st
+  e = ensure_lanes(p);
+  if (e == hipSuccess) e = hipEventRecord(p.lane_ev[0], st);
+  for (int l = 0; l < lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(p.lane_st[l], p.lane_ev[0], 0);
+  if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: fork", e);
+  // instances dealt round robin to the lanes
+  for (size_t k = 0; k < p.inst.size(); ++k) {
+    InstHost &ih = p.inst[k];
+    const int l = (int)(k % (size_t)lanes);
+    const fzp_status_t s =
+        enqueue_instance(p, ih, l, ws, (double2 *)roi_dev + ih.roi_off, row_begin, row_end, p.lane_st[l]);
+    if (s != FZP_OK) return s;
+  }
+  // join: st waits for every lane
+  for (int l = 0; l < lanes && e == hipSuccess; ++l) {
+    e = hipEventRecord(p.lane_ev[1 + l], p.lane_st[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p.lane_ev[1 + l], 0);
+  }
+  if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: join", e);
   return FZP_OK;
 }
 
@@ -565,4 +634,204 @@ extern "C" fzp_status_t fzp_profile_read(fzp_plan_t h, double *row_ms, int64_t *
     p.row_n = p.col_n = p.aux_n = 0;
   }
   return FZP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph capture of a whole propagation
+// ---------------------------------------------------------------------------
+
+struct fzp_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~fzp_graph_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+extern "C" fzp_status_t fzp_graph_create(fzp_plan_t h, void *workspace, double *roi_dev, fzp_graph_t *out) {
+  if (!h || !workspace || !roi_dev || !out) return fail(FZP_E_INVAL, "fzp_graph_create: NULL argument");
+  *out = nullptr;
+  Plan &p = h->plan;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail("fzp_graph_create: stream", e);
+  // tables, kernel attributes and lane streams exist before the capture starts
+  fzp_status_t s = fzp_prepare(h, workspace, cs);
+  if (s == FZP_OK) {
+    e = hipStreamSynchronize(cs);
+    if (e == hipSuccess) e = ensure_lanes(p);
+    if (e != hipSuccess) s = hip_fail("fzp_graph_create: prepare", e);
+  }
+  if (s != FZP_OK) {
+    (void)hipStreamDestroy(cs);
+    return s;
+  }
+  auto *g = new (std::nothrow) fzp_graph_s;
+  if (!g) {
+    (void)hipStreamDestroy(cs);
+    return fail(FZP_E_NOMEM, "fzp_graph_create: out of host memory");
+  }
+  const bool prof = p.profile;
+  p.profile = false;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = fzp_propagate_roi_range(h, workspace, roi_dev, 0, p.ap.N, 0, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (s == FZP_OK && e2 != hipSuccess) s = hip_fail("fzp_graph_create: end capture", e2);
+    if (s == FZP_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) s = hip_fail("fzp_graph_create: instantiate", e);
+    }
+  } else {
+    s = hip_fail("fzp_graph_create: begin capture", e);
+  }
+  p.profile = prof;
+  (void)hipStreamDestroy(cs);
+  if (s != FZP_OK) {
+    delete g;
+    return s;
+  }
+  *out = g;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_graph_launch(fzp_graph_t g, void *stream) {
+  if (!g || !g->exec) return fail(FZP_E_INVAL, "fzp_graph_launch: NULL graph");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail("fzp_graph_launch", e);
+  return FZP_OK;
+}
+
+extern "C" void fzp_graph_destroy(fzp_graph_t g) { delete g; }
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void set_seg_len(Plan &p, int64_t seg_len) {
+  p.seg_len = seg_len;
+  for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
+}
+
+// Plan shape and device: what the best decomposition depends on.
+std::string tune_key(const Plan &p) {
+  std::ostringstream k;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char &c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  k << "fzp1/" << arch << "/N" << p.ap.N << "/path" << p.opt.path << "/chunk" << p.chunk_rows << "/L"
+    << p.lanes_max;
+  // the multiset of (M, deformed) over instances, in instance order
+  for (const auto &ih : p.inst) k << "/" << ih.dev.M << (ih.dev.n_creases > 0 ? "c" : "f");
+  return k.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, int64_t &seg_len, int32_t &lanes) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    int64_t sl;
+    int32_t ln;
+    if (ls >> k >> sl >> ln && k == key) {
+      seg_len = sl;
+      lanes = ln;
+      found = true;  // the last entry wins
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_dev, void *stream,
+                                     const char *cache_path, int64_t *seg_len_out, int32_t *lanes_out,
+                                     double *ms_out) {
+  if (!h || !workspace || !roi_dev) return fail(FZP_E_INVAL, "fzp_autotune: NULL argument");
+  try {
+    Plan &p = h->plan;
+    hipStream_t st = (hipStream_t)stream;
+    const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
+    const int64_t seg0 = p.seg_len;
+    // candidates: the default segment and its doublings (fewer partial planes,
+    // so they fit the plan's T buffers), and every lane count
+    std::vector<int64_t> segs{seg0};
+    if (split)
+      for (int64_t sl = 2 * seg0; sl <= 65536 && sl < 2 * p.ap.N; sl *= 2) segs.push_back(sl);
+    const std::string key = tune_key(p);
+    int64_t best_seg = seg0;
+    int32_t best_lanes = p.lanes_max;
+    double best_ms = 0.0;
+    if (cache_lookup(cache_path, key, best_seg, best_lanes) && best_lanes >= 1 && best_lanes <= p.lanes_max &&
+        std::find(segs.begin(), segs.end(), best_seg) != segs.end()) {
+      set_seg_len(p, best_seg);
+      p.lanes = best_lanes;
+    } else {
+      const bool prof = p.profile;
+      p.profile = false;
+      hipEvent_t a = nullptr, b = nullptr;
+      hipError_t e = hipEventCreate(&a);
+      if (e == hipSuccess) e = hipEventCreate(&b);
+      fzp_status_t s = e == hipSuccess ? FZP_OK : hip_fail("fzp_autotune: events", e);
+      best_ms = std::numeric_limits<double>::infinity();
+      for (int32_t ln = 1; ln <= p.lanes_max && s == FZP_OK; ++ln) {
+        for (int64_t sl : segs) {
+          set_seg_len(p, sl);
+          p.lanes = ln;
+          // one untimed run (first use of the lanes, caches), then one timed run
+          s = fzp_propagate_roi(h, workspace, roi_dev, stream);
+          if (s != FZP_OK) break;
+          e = hipEventRecord(a, st);
+          if (e != hipSuccess) {
+            s = hip_fail("fzp_autotune: record", e);
+            break;
+          }
+          s = fzp_propagate_roi(h, workspace, roi_dev, stream);
+          if (s != FZP_OK) break;
+          e = hipEventRecord(b, st);
+          if (e == hipSuccess) e = hipEventSynchronize(b);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+          if (e != hipSuccess) {
+            s = hip_fail("fzp_autotune: timing", e);
+            break;
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_seg = sl;
+            best_lanes = ln;
+          }
+        }
+      }
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      p.profile = prof;
+      set_seg_len(p, best_seg);
+      p.lanes = best_lanes;
+      if (s != FZP_OK) return s;
+      if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (f) f << key << " " << best_seg << " " << best_lanes << "\n";
+      }
+    }
+    if (seg_len_out) *seg_len_out = best_seg;
+    if (lanes_out) *lanes_out = best_lanes;
+    if (ms_out) *ms_out = best_ms;
+    return FZP_OK;
+  } catch (const std::exception &ex) {
+    return fail(FZP_E_INVAL, std::string("fzp_autotune: ") + ex.what());
+  } catch (...) {
+    return fail(FZP_E_INVAL, "fzp_autotune: unknown error");
+  }
 }
