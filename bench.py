@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch of the 20 mm element")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train and judge the learned surrogate (20k + 1k CZT solves)")
+    ap.add_argument("--surrogate-epochs", type=int, default=300)
     return ap.parse_args()
 
 
@@ -250,6 +253,10 @@ def main():
         out["speedup_split_vs_fp64"] = round(fp64["ms"] / split["ms"], 3)
     if not args.no_batch:
         out["batch64"] = run_batch(args, dev)
+    if args.surrogate:
+        from paper_2609_01978_amd import surrogate as SG
+        sw = workload("surrogate")
+        out["surrogate"] = SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)

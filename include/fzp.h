@@ -207,6 +207,60 @@ fzp_status_t fzp_autotune(fzp_plan_t p, void *workspace, double *roi_dev, void *
 
 void fzp_destroy(fzp_plan_t p);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate.  The paper motivates full 2-D simulation by membrane
+ * deformations (introduction) and gives no learned model; the library adds a
+ * multilayer perceptron from crease parameters and the wavelength to the ROI
+ * log-intensity, trained on the propagation's own outputs, with the CZT as
+ * judge and fallback:
+ *   z1 = W1 x + b1, h1 = silu(z1); z2 = W2 h1 + b2, h2 = silu(z2); y = W3 h2 + b3,
+ *   silu(z) = z / (1 + e^{-z}),  loss = sum (y - t)^2 / (B n_out),
+ * Adam updates (Kingma & Ba 2015, Algorithm 1; beta1 0.9, beta2 0.999,
+ * eps 1e-8).  Parameters are one flat float32 vector W1 [H][n_in], b1 [H],
+ * W2 [H][H], b2 [H], W3 [n_out][H], b3 [n_out] (row-major).  The products run
+ * on the matrix cores with BF16 weights, activations and gradients and float32
+ * accumulation; masters, moments, biases and the loss are float32.
+ * Row-major device arrays: x [batch][n_in], t and y [batch][n_out],
+ * dx [batch][n_in].  All calls are asynchronous on `stream`; none allocates
+ * device memory (the caller's workspace holds everything).
+ * ------------------------------------------------------------------------ */
+typedef struct fzp_mlp_s *fzp_mlp_t;
+
+/* Host only: sizes (n_in 1..4096, n_hidden 1..8192, n_out 1..2^20, batch_max
+ * 1..65536); FZP_E_INVAL otherwise. */
+fzp_status_t fzp_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch_max, fzp_mlp_t *out);
+/* Workspace bytes (256-byte aligned buffer owned by the caller) and the
+ * parameter count. */
+fzp_status_t fzp_mlp_info(fzp_mlp_t m, size_t *workspace_bytes, int64_t *n_params);
+/* Load parameters (device float32, n_params) into the workspace, refresh the
+ * BF16 copies and reset the optimizer state; fzp_mlp_get_params copies them out. */
+fzp_status_t fzp_mlp_set_params(fzp_mlp_t m, void *workspace, const float *params_dev, void *stream);
+fzp_status_t fzp_mlp_get_params(fzp_mlp_t m, void *workspace, float *params_dev, void *stream);
+/* y = network(x) for 1 <= batch <= batch_max rows. */
+fzp_status_t fzp_mlp_forward(fzp_mlp_t m, void *workspace, const float *x_dev, int32_t batch, float *y_dev,
+                             void *stream);
+/* Forward, loss against t, and the gradients: grads_dev (n_params, the
+ * parameter layout), dx_dev (may be NULL), loss_dev (one float, may be NULL);
+ * y_dev receives the forward output.  No update. */
+fzp_status_t fzp_mlp_backward(fzp_mlp_t m, void *workspace, const float *x_dev, const float *t_dev, int32_t batch,
+                              float *y_dev, float *grads_dev, float *dx_dev, float *loss_dev, void *stream);
+/* One training step: forward, backward, Adam update with learning rate lr
+ * (the step counter lives in the model and restarts at fzp_mlp_set_params). */
+fzp_status_t fzp_mlp_train_step(fzp_mlp_t m, void *workspace, const float *x_dev, const float *t_dev,
+                                int32_t batch, float *y_dev, float lr, float *loss_dev, void *stream);
+/* One Adam update from given gradients (device float32, n_params). */
+fzp_status_t fzp_mlp_adam_update(fzp_mlp_t m, void *workspace, const float *grads_dev, float lr, void *stream);
+void fzp_mlp_destroy(fzp_mlp_t m);
+
+/* Training targets and back: out = ln(|U|^2 / i0 + floor) for n_complex ROI
+ * samples (float32 out), and U = sqrt(max(i0 (e^y - floor), 0)) + 0i (float64
+ * complex, so that fzp_metrics reads predicted intensities).  i0 > 0,
+ * floor > 0. */
+fzp_status_t fzp_log_intensity(const double *roi_dev, int64_t n_complex, double i0, double floor_, float *out_dev,
+                               void *stream);
+fzp_status_t fzp_field_from_log_intensity(const float *y_dev, int64_t n_complex, double i0, double floor_,
+                                          double *roi_dev, void *stream);
+
 /* Thread-local message of the last non-OK status on this thread. */
 const char *fzp_last_error(void);
 

@@ -34,7 +34,9 @@ EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
     "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
-    "fzp_graph_destroy", "fzp_autotune",
+    "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
+    "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
+    "fzp_mlp_destroy", "fzp_log_intensity", "fzp_field_from_log_intensity",
 ]
 
 
@@ -126,6 +128,23 @@ def load_library() -> ctypes.CDLL:
     lib.fzp_autotune.restype = st
     lib.fzp_destroy.argtypes = [P]
     lib.fzp_destroy.restype = None
+    i32, i64, f32, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    lib.fzp_mlp_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(P)]
+    lib.fzp_mlp_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i64)]
+    lib.fzp_mlp_set_params.argtypes = [P, P, P, P]
+    lib.fzp_mlp_get_params.argtypes = [P, P, P, P]
+    lib.fzp_mlp_forward.argtypes = [P, P, P, i32, P, P]
+    lib.fzp_mlp_backward.argtypes = [P, P, P, P, i32, P, P, P, P, P]
+    lib.fzp_mlp_train_step.argtypes = [P, P, P, P, i32, P, f32, P, P]
+    lib.fzp_mlp_adam_update.argtypes = [P, P, P, f32, P]
+    lib.fzp_log_intensity.argtypes = [P, i64, dbl, dbl, P, P]
+    lib.fzp_field_from_log_intensity.argtypes = [P, i64, dbl, dbl, P, P]
+    for name in ("fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params", "fzp_mlp_get_params", "fzp_mlp_forward",
+                 "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update", "fzp_log_intensity",
+                 "fzp_field_from_log_intensity"):
+        getattr(lib, name).restype = st
+    lib.fzp_mlp_destroy.argtypes = [P]
+    lib.fzp_mlp_destroy.restype = None
     lib.fzp_last_error.argtypes = []
     lib.fzp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -294,3 +313,88 @@ class Graph:
         if g is not None and g.value:
             self._lib.fzp_graph_destroy(g)
             self._g = None
+
+
+class MLP:
+    """The surrogate network (fzp_mlp_*): float32 tensors in, float32 out, on the GPU."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, batch_max: int, device="cuda"):
+        import torch
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self._lib, self._lib.fzp_mlp_create(n_in, n_hidden, n_out, batch_max, ctypes.byref(h)))
+        self._h = h
+        b, n = ctypes.c_size_t(), ctypes.c_int64()
+        _check(self._lib, self._lib.fzp_mlp_info(h, ctypes.byref(b), ctypes.byref(n)))
+        self.n_in, self.n_hidden, self.n_out, self.batch_max = n_in, n_hidden, n_out, batch_max
+        self.n_params = int(n.value)
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=device)
+        self._loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self._y = torch.empty((batch_max, n_out), dtype=torch.float32, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fzp_mlp_destroy(h)
+            self._h = None
+
+    def set_params(self, theta, stream=None):
+        assert theta.dtype.is_floating_point and theta.numel() == self.n_params and theta.is_contiguous()
+        _check(self._lib, self._lib.fzp_mlp_set_params(self._h, _ptr(self.ws), _ptr(theta), _stream_handle(stream)))
+
+    def get_params(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.ws.device)
+        _check(self._lib, self._lib.fzp_mlp_get_params(self._h, _ptr(self.ws), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def _rows(self, x):
+        assert x.dtype == self._y.dtype and x.is_contiguous() and x.shape[1] == self.n_in
+        b = int(x.shape[0])
+        assert 1 <= b <= self.batch_max
+        return b
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        b = self._rows(x)
+        y = out if out is not None else torch.empty((b, self.n_out), dtype=torch.float32, device=x.device)
+        _check(self._lib, self._lib.fzp_mlp_forward(self._h, _ptr(self.ws), _ptr(x), b, _ptr(y),
+                                                    _stream_handle(stream)))
+        return y
+
+    def backward(self, x, t, stream=None):
+        """(loss tensor[1], grads[n_params], dx[batch, n_in], y[batch, n_out]); no update."""
+        import torch
+        b = self._rows(x)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        dx = torch.empty((b, self.n_in), dtype=torch.float32, device=x.device)
+        y = torch.empty((b, self.n_out), dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(self._lib, self._lib.fzp_mlp_backward(self._h, _ptr(self.ws), _ptr(x), _ptr(t), b, _ptr(y), _ptr(g),
+                                                     _ptr(dx), _ptr(loss), _stream_handle(stream)))
+        return loss, g, dx, y
+
+    def train_step(self, x, t, lr: float, stream=None):
+        """One forward/backward/Adam step; returns the loss as a device tensor[1] (before the update)."""
+        b = self._rows(x)
+        _check(self._lib, self._lib.fzp_mlp_train_step(self._h, _ptr(self.ws), _ptr(x), _ptr(t), b, _ptr(self._y),
+                                                       float(lr), _ptr(self._loss), _stream_handle(stream)))
+        return self._loss
+
+    def adam_update(self, grads, lr: float, stream=None):
+        _check(self._lib, self._lib.fzp_mlp_adam_update(self._h, _ptr(self.ws), _ptr(grads), float(lr),
+                                                        _stream_handle(stream)))
+
+
+def log_intensity(roi, n_complex: int, i0: float, floor: float, out, stream=None):
+    """out[:n] = ln(|U|^2/i0 + floor) on the GPU (roi: float64 interleaved complex)."""
+    lib = load_library()
+    _check(lib, lib.fzp_log_intensity(_ptr(roi), int(n_complex), float(i0), float(floor), _ptr(out),
+                                      _stream_handle(stream)))
+
+
+def field_from_log_intensity(y, n_complex: int, i0: float, floor: float, roi, stream=None):
+    """roi[:n] = sqrt(max(i0 (e^y - floor), 0)) + 0i on the GPU."""
+    lib = load_library()
+    _check(lib, lib.fzp_field_from_log_intensity(_ptr(y), int(n_complex), float(i0), float(floor), _ptr(roi),
+                                                 _stream_handle(stream)))

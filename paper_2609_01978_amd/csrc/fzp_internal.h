@@ -99,6 +99,9 @@ struct Plan {
   ~Plan();
 };
 
+// Thread-local text returned by fzp_last_error (fzp_plan.cpp).
+void set_last_error(const std::string &msg);
+
 // ---- launchers (fzp_fft.hip, fzp_gemm.hip, fzp_metrics.hip) ----
 hipError_t launch_build_tables(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
 hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);

@@ -92,6 +92,8 @@ using fzp::Plan;
 
 extern "C" const char *fzp_last_error(void) { return g_err.c_str(); }
 
+void fzp::set_last_error(const std::string &msg) { g_err = msg; }
+
 extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t *inst, int32_t n_inst,
                                  const fzp_options_t *opt, fzp_plan_t *out) {
   try {

@@ -126,3 +126,20 @@ def test_split_creased_plan_layout():
     table = 2 * (2 * 512) * w["N"] * 2               # hi/lo planes of the N x 2M BF16 operand table
     assert bent.workspace_size >= table + c * w["N"] * 8
     assert flat.workspace_size < table + c * w["N"] * 8
+
+
+def test_mlp_create_and_layout():
+    from oracle import mlp_oracle as Q
+    lib = P.load_library()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.fzp_mlp_create(33, 512, 16384, 256, ctypes.byref(h)) == P.FZP_OK
+    b, n = ctypes.c_size_t(), ctypes.c_int64()
+    assert lib.fzp_mlp_info(h, ctypes.byref(b), ctypes.byref(n)) == P.FZP_OK
+    assert n.value == Q.param_count(33, 512, 16384) == 8685056
+    # masters, BF16 copies, two moments, gradients, activations of 256 rows
+    assert b.value >= n.value * (4 + 2 + 4 + 4 + 4) + 256 * 16384 * 6
+    lib.fzp_mlp_destroy(h)
+    for bad in ((0, 512, 16384, 256), (33, 512, 16384, 0), (33, 0, 10, 1), (33, 10, 10, 70000)):
+        assert lib.fzp_mlp_create(*bad, ctypes.byref(h)) == P.FZP_E_INVAL
+    assert b"sizes" in lib.fzp_last_error()
