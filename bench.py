@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and judge the learned surrogate (20k + 1k CZT solves)")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -137,6 +139,18 @@ def main():
     import torch
     import paper_2609_01978_amd as P
     from fzp_inputs import workload
+
+    if args.copy_calibration:
+        # 1 GiB read + 1 GiB written per copy; FETCH_SIZE / WRITE_SIZE of this
+        # kernel scale the counters of the library's kernels to bytes
+        n = 1 << 30
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
 
     w = workload(args.workload)
     ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])

@@ -68,6 +68,11 @@ typedef int32_t fzp_status_t;
 
 /* Plan flags. */
 #define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */
+/* Split path, binary stripes: the GEMM variant a plan starts with (fzp_autotune may
+ * change it).  Without either flag: variant 2, the 512-row tile (one work-group per
+ * compute unit) with an 8-stage LDS pipeline. */
+#define FZP_FLAG_BIN_TILE_256 2       /* variant 1: 256-row tile, two work-groups per compute unit */
+#define FZP_FLAG_BIN_SHALLOW 4        /* variant 0: 512-row tile with a 4-stage LDS pipeline */
 
 typedef struct {
   double D;          /* aperture diameter */
@@ -193,17 +198,20 @@ void fzp_graph_destroy(fzp_graph_t g);
 /* Autotuner of the split path's GEMM work decomposition.  Candidates are the
  * K-segment length of a work-group tile (the plan's default and its doublings
  * up to 65536 columns; longer segments mean fewer float32 partial planes for
- * the column pass but fewer independent tiles) and the number of concurrent
- * lanes (1 .. options.lanes).  Each candidate runs one full propagation on
- * `stream`, timed with HIP events; the fastest is kept in the plan.  With a
- * non-NULL `cache_path` the choice is looked up first in that text file (one
- * "key seg_len lanes" line per plan shape and GPU) and appended when new.
- * `roi_dev` is overwritten.  seg_len_out / lanes_out / ms_out (the winning
- * time, 0 when taken from the cache) may be NULL.  The FP64 path has nothing
- * to tune except lanes.  Errors: FZP_E_INVAL, FZP_E_DEVICE. */
+ * the column pass but fewer independent tiles), the binary-stripe GEMM variant
+ * (0: 512-row tile, one work-group per compute unit, 4-stage LDS pipeline;
+ * 1: 256-row tile, two work-groups per compute unit; 2: 512-row tile with an
+ * 8-stage pipeline), and the number of concurrent lanes (1 .. options.lanes).  Each candidate runs one
+ * full propagation on `stream`, timed with HIP events; the fastest is kept in
+ * the plan.  With a non-NULL `cache_path` the choice is looked up first in
+ * that text file (one "key seg_len lanes variant" line per plan shape and
+ * GPU) and appended when new.  `roi_dev` is overwritten.  The outputs
+ * (segment, lanes, variant, and the winning time in ms, 0 when taken from
+ * the cache) may be NULL.  The FP64 path has nothing to tune except lanes.
+ * Errors: FZP_E_INVAL, FZP_E_DEVICE. */
 fzp_status_t fzp_autotune(fzp_plan_t p, void *workspace, double *roi_dev, void *stream,
                           const char *cache_path, int64_t *seg_len_out, int32_t *lanes_out,
-                          double *ms_out);
+                          int32_t *variant_out, double *ms_out);
 
 void fzp_destroy(fzp_plan_t p);
 

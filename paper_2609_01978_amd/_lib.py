@@ -29,6 +29,8 @@ STATUS_NAMES = {0: "FZP_OK", -1: "FZP_E_INVAL", -2: "FZP_E_SAMPLING", -3: "FZP_E
 PATH_FP64_BLUESTEIN = 0
 PATH_SPLIT_BF16 = 1
 FLAG_ALLOW_UNDERSAMPLED = 1
+FLAG_BIN_TILE_256 = 2
+FLAG_BIN_SHALLOW = 4
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
@@ -124,7 +126,8 @@ def load_library() -> ctypes.CDLL:
     lib.fzp_graph_destroy.argtypes = [P]
     lib.fzp_graph_destroy.restype = None
     lib.fzp_autotune.argtypes = [P, P, P, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
-                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
     lib.fzp_autotune.restype = st
     lib.fzp_destroy.argtypes = [P]
     lib.fzp_destroy.restype = None
@@ -174,7 +177,7 @@ class Plan:
 
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
                  chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
-                 lanes: int = 0):
+                 lanes: int = 0, variant: int = 2):
         lib = load_library()
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
@@ -195,7 +198,8 @@ class Plan:
                               n_creases=ncr, creases=ctypes.cast(cbuf, ctypes.POINTER(Crease)))
         p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16}[path] if isinstance(path, str) else int(path)
         opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
-                      flags=FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0, lanes=int(lanes))
+                      flags=(FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0)
+                      | {0: FLAG_BIN_SHALLOW, 1: FLAG_BIN_TILE_256, 2: 0}[variant], lanes=int(lanes))
         h = ctypes.c_void_p()
         _check(lib, lib.fzp_plan(ctypes.byref(ap), arr, n, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -283,12 +287,13 @@ class Plan:
         return [out[k].as_dict() for k in range(self.n_instances)]
 
     def autotune(self, ws, roi, cache_path: Optional[str] = None, stream=None) -> dict:
-        """Pick the split GEMM's K-segment length and the lane count by timing (overwrites roi)."""
-        sl, ln, ms = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        """Pick the split GEMM's K-segment length, variant and lane count by timing (overwrites roi)."""
+        sl, ln, tl, ms = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         cp = None if cache_path is None else os.fsencode(cache_path)
         _check(self._lib, self._lib.fzp_autotune(self._h, _ptr(ws), _ptr(roi), _stream_handle(stream), cp,
-                                                 ctypes.byref(sl), ctypes.byref(ln), ctypes.byref(ms)))
-        return dict(seg_len=sl.value, lanes=ln.value, ms=ms.value)
+                                                 ctypes.byref(sl), ctypes.byref(ln), ctypes.byref(tl),
+                                                 ctypes.byref(ms)))
+        return dict(seg_len=sl.value, lanes=ln.value, variant=tl.value, ms=ms.value)
 
     def graph(self, ws, roi) -> "Graph":
         """One whole propagation of the plan captured as a HIP graph bound to ws and roi."""

@@ -72,21 +72,22 @@ __global__ __launch_bounds__(256) void k_build_split_table(InstDev d, uint16_t *
 // single float64 product the reference rule uses (Sec. 2.2, Eq. 4).  Each
 // element is evaluated once here instead of once per GEMM column tile.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin, int64_t row_end, int W,
-                                                   uint32_t *__restrict__ bits) {
+__global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin, int64_t row_end, int64_t rows_pad,
+                                                   int W, uint32_t *__restrict__ bits) {
   const int64_t N = d.N;
   const int Nm1 = (int)(N - 1);
   const double kappa = d.kappa;
   const uint32_t flip = d.centre_open ? 0xffffffffu : 0u;
   const int64_t rows = row_end - row_begin;
   const int64_t rl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // thread = one row
-  if (rl >= rows) return;
+  if (rl >= rows_pad) return;
+  // rows past the chunk (up to the padded row count) get empty chords: zero words
   const int64_t row = row_begin + rl;
   const double cj = (double)(2 * row - N + 1);
   const double bj = cj * cj;
   int rlo = 0, rhi = 0;
   const double rem = d.kmax - bj;
-  if (rem >= 0.0) {
+  if (rl < rows && rem >= 0.0) {
     int m = (int)sqrt(rem);
     while ((double)(m + 1) * (double)(m + 1) <= rem) ++m;
     while (m > 0 && (double)m * (double)m > rem) --m;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
       const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
       v = (v ^ flip) & valid;
     }
-    bits[(int64_t)w * rows + rl] = v;
+    bits[(int64_t)w * rows_pad + rl] = v;
   }
 }
 
@@ -138,15 +139,45 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
 // in the order chunk ^ swz(r), which keeps the MFMA operand reads (32
 // consecutive rows, one chunk) free of bank conflicts without padding.
 // ---------------------------------------------------------------------------
-constexpr int kThreads = 512;
-constexpr int kTR = 512;     // rows per tile
+constexpr int kThreads = 512;   // threads of the 512-row variant and of the complex kernel
 constexpr int kTC = 128;     // real columns per tile (64 complex ROI columns)
 constexpr int kKT = 32;      // K columns per pipeline stage
 constexpr int kRowB = 64;    // LDS bytes per slab row of a stage
 constexpr int kBBytes = 2 * kTC * kRowB;           // 16384 (hi and lo planes)
-constexpr int kBitsBytes = kTR * 4;                // one mask word per tile row
 constexpr int kRing = 4, kAhead = 3;
-constexpr int kLdsBytes = kRing * (kBBytes + kBitsBytes);  // 73728
+
+// Binary-stripe GEMM variants, by WR = waves along the rows: the tile has
+// 128 WR rows and 2 WR waves (WR = 4: 512 rows, 8 waves, one work-group per
+// CU; WR = 2: 256 rows, 4 waves, two work-groups per CU, so that one
+// work-group's barrier and pipeline start-up are covered by the other's
+// MFMAs).  Each wave copies 8 / WR slab pieces and one mask-word piece per
+// stage.
+template <int WR, int RING = kRing> struct BinTile {
+  static constexpr int rows = 128 * WR;
+  static constexpr int threads = 128 * WR;
+  static constexpr int waves = 2 * WR;
+  static constexpr int per_cu = 4 / WR;
+  static constexpr int slab_copies = 8 / WR;               // 1 KiB pieces per wave
+  static constexpr int copies = slab_copies + 1;          // + one mask-word piece
+  static constexpr int bits_bytes = rows * 4;             // one mask word per tile row
+  static constexpr int ring = RING;                       // LDS stages
+  static constexpr int ahead = RING - 1;                  // stages copied ahead of use
+  static constexpr int lds = RING * (kBBytes + bits_bytes);
+  static constexpr int round = 32 * per_cu;               // concurrent work-groups per XCD
+  // copies a wave may leave outstanding at the end of a stage: those of the
+  // RING - 2 stages after the next one
+  static constexpr int wait = (RING - 2) * copies;
+};
+
+// s_waitcnt vmcnt(N) + s_barrier for the outstanding-copy counts used above.
+template <int N> __device__ __forceinline__ void wait_barrier() {
+  static_assert(N == 6 || N == 10 || N == 12 || N == 18 || N == 20, "add the count");
+  if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 10) asm volatile("s_waitcnt vmcnt(10) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 18) asm volatile("s_waitcnt vmcnt(18) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 20) asm volatile("s_waitcnt vmcnt(20) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 __device__ __forceinline__ u32x4 lds_ld16(const char *p) { return *(const u32x4 *)p; }
@@ -161,16 +192,16 @@ __device__ __forceinline__ void stage_barrier() {
 }
 
 // 8 mask bits (one byte, column order) -> 8 packed BF16 values (1.0 / 0).
-// y = x | x << 15 puts bit 2p at bit 2p and bit 2p+1 at bit 2p+16, so
-// (y >> 2p) & 0x10001 is the pair (b_2p, b_2p+1) as two 16-bit integers,
-// and multiplying by 0x3f80 turns each 1 into BF16 1.0.
+// y = x | x << 15 puts bit 2p at bit 2p and bit 2p+1 at bit 2p+16; masking
+// those two bits and multiplying by 0x3f80 / 4^p (an integer for p <= 3)
+// moves them to bits 0 and 16 as BF16 1.0 = 0x3f80: two operations per pair.
 __device__ __forceinline__ bf16x8 expand8(uint32_t x) {
   const uint32_t y = x | (x << 15);
   u32x4 v;
-  v[0] = (y & 0x10001u) * 0x3f80u;
-  v[1] = ((y >> 2) & 0x10001u) * 0x3f80u;
-  v[2] = ((y >> 4) & 0x10001u) * 0x3f80u;
-  v[3] = ((y >> 6) & 0x10001u) * 0x3f80u;
+  v[0] = (y & 0x00010001u) * 0x3f80u;
+  v[1] = (y & 0x00040004u) * 0x0fe0u;
+  v[2] = (y & 0x00100010u) * 0x03f8u;
+  v[3] = (y & 0x00400040u) * 0x00feu;
   return __builtin_bit_cast(bf16x8, v);
 }
 
@@ -194,12 +225,17 @@ __device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t
   hi = (hi2 / 2 < N - 1 ? hi2 / 2 : N - 1) + 1;
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
+template <int WR, int RING>
+__global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
                                                                 int n_rt, int n_ct, int seg_lo, int n_seg,
                                                                 const uint32_t *__restrict__ bits, int W,
                                                                 int64_t bits_rows, float *__restrict__ T,
                                                                 int64_t seg_stride_f) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
+  using BT = BinTile<WR, RING>;
+  constexpr int kTR = BT::rows;
+  constexpr int kBitsBytes = BT::bits_bytes;
+  constexpr int kRing = BT::ring, kAhead = BT::ahead;
   char *const bbuf = lds;                            // kRing x kBBytes
   char *const wbuf = lds + kRing * kBBytes;          // kRing x kBitsBytes
   const int tid = threadIdx.x;
@@ -212,7 +248,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
   // L2 while every XCD draws from all K segments (whose work differs).
   const int G = n_rt * n_ct * n_seg;
   const int slot = blockIdx.x >> 3;
-  const int g = (slot >> 5) * 256 + (blockIdx.x & 7) * 32 + (slot & 31);
+  const int g = (slot / BT::round) * (8 * BT::round) + (blockIdx.x & 7) * BT::round + (slot % BT::round);
   if (g >= G) return;
   const int rt = g % n_rt;
   const int ct = (g / n_rt) % n_ct;
@@ -232,19 +268,19 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
   if (k_lo < s_lo) k_lo = s_lo;
   if (k_hi > s_hi) k_hi = s_hi;
 
-  // ---- bit-word copy role: lane tid copies the word of tile row tid (rows past
-  // the chunk read its last row; their words are zeroed when expanded)
-  const int64_t wrow = min(r0 + tid, row_end - 1) - row_begin;
-  const uint32_t *wsrc = bits + wrow;
-  // ---- slab-copy role: wave w copies slab rows [32 w, 32 w + 32) (2 direct loads
-  // of 16 rows); lane L carries chunk L&3 of row 16 x + L/4 of its block, read
-  // from global chunk (L&3) ^ swz(row) so the LDS image is the swizzled layout.
-  // Columns past 2M read column 0 instead: they only feed accumulator columns
-  // that are never stored.
-  const uint16_t *bsrc[2];
+  // ---- bit-word copy role: lane tid copies the word of tile row tid (the mask
+  // buffer's rows are padded to a multiple of 512 with zero words)
+  const uint32_t *wsrc = bits + (r0 + tid - row_begin);
+  // ---- slab-copy role: wave w copies slab rows [16 c w, 16 c (w + 1)) (c direct
+  // loads of 16 rows, c = 8 / WR); lane L carries chunk L&3 of row 16 x + L/4 of
+  // its block, read from global chunk (L&3) ^ swz(row) so the LDS image is the
+  // swizzled layout.  Columns past 2M read column 0 instead: they only feed
+  // accumulator columns that are never stored.
+  constexpr int SC = BT::slab_copies;
+  const uint16_t *bsrc[SC];
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int R = (wave * 2 + x) * 16 + (lane >> 2);
+  for (int x = 0; x < SC; ++x) {
+    const int R = (wave * SC + x) * 16 + (lane >> 2);
     const int plane = R / kTC, col = R % kTC;
     const int gc = c0 + col < M2 ? c0 + col : 0;
     const int chunk = (lane & 3) ^ swz(R);
@@ -258,10 +294,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
   // byte offsets of this lane's slab chunks for K-step ks (row & 31 == l32 everywhere)
   const int cks0 = ((0 + lhi) ^ lsw) << 4, cks1 = ((2 + lhi) ^ lsw) << 4;
   const int brow = (wc * 64 + l32) * kRowB;
-  // this lane's 4 mask rows: tile rows wr*128 + rb*32 + l32
-  uint32_t row_ok = 0;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) row_ok |= (r0 + wr * 128 + rb * 32 + l32 < row_end ? 1u : 0u) << rb;
 
   f32x16 acc[4][2];
 #pragma unroll
@@ -280,9 +312,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
     auto copy_stage = [&](int s) {
       const int k = min(kb + s * kKT, klast);
       const int64_t kofs = (int64_t)(k >> 5) * M2 * 32;  // 32-column block of the table
-      char *dst = bbuf + (s % kRing) * kBBytes + wave * 2 * 1024;
+      char *dst = bbuf + (s % kRing) * kBBytes + wave * SC * 1024;
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < SC; ++x)
         __builtin_amdgcn_global_load_lds((const void *)(bsrc[x] + kofs),
                                          (__attribute__((address_space(3))) void *)(dst + x * 1024), 16, 0, 0);
       const int wi = min((kb + s * kKT) >> 5, W - 1);
@@ -292,14 +324,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
                                        4, 0, 0);
     };
     for (int s = 0; s < kAhead; ++s) copy_stage(s);
-    asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+    wait_barrier<BT::wait>();
     for (int s = 0; s < nst; ++s) {
       copy_stage(s + kAhead);
       const char *sb = bbuf + (s % kRing) * kBBytes + brow;
       const uint32_t *sw = (const uint32_t *)(wbuf + (s % kRing) * kBitsBytes) + wr * 128 + l32;
       uint32_t word[4];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) word[rb] = (row_ok >> rb & 1u) ? sw[rb * 32] : 0u;
+      for (int rb = 0; rb < 4; ++rb) word[rb] = sw[rb * 32];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         const int cofs = ks ? cks1 : cks0;
@@ -324,7 +356,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split(InstDev d, int64
           for (int cb = 0; cb < 2; ++cb)
             acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
       }
-      stage_barrier();
+      wait_barrier<BT::wait>();
     }
     // drain the copies still in flight before the work-group retires its LDS
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -603,8 +635,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, 
 hipError_t init_split_attributes() {
   static bool done = false;  // set once per process (the attributes are per function)
   if (done) return hipSuccess;
-  hipError_t e =
-      hipFuncSetAttribute((const void *)k_row_pass_split, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 4>::lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            BinTile<4, 8>::lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            BinTile<2, 4>::lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kCLdsBytes);
@@ -622,7 +660,12 @@ hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws,
 
 int split_segments(const InstDev &d) { return (int)((d.Npad + d.seg_len - 1) / d.seg_len); }
 
-size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows) { return (size_t)chunk_rows * (size_t)(d.Npad / 32) * 4; }
+// Mask-bit rows are padded to a multiple of the largest binary tile (512 rows).
+int64_t bits_rows_pad(int64_t rows) { return (rows + 511) / 512 * 512; }
+
+size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows) {
+  return (size_t)bits_rows_pad(chunk_rows) * (size_t)(d.Npad / 32) * 4;
+}
 
 // Union of the disc chords of rows [row_begin, row_end): the chord of the row
 // nearest the axis, aperture columns [lo, hi); lo = hi = 0 when no row meets
@@ -665,30 +708,42 @@ hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
   const int W = (int)(d.Npad / 32);
-  const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)((W + 63) / 64));
-  hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, W, bits);
+  const int64_t rows_pad = bits_rows_pad(rows);
+  const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)((W + 63) / 64));
+  hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, W, bits);
   return hipGetLastError();
 }
+
+namespace {
+template <int WR, int RING>
+hipError_t launch_bin(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
+                      const uint32_t *bits, int seg_lo, int n_seg, hipStream_t st) {
+  using BT = BinTile<WR, RING>;
+  const int64_t rows = row_end - row_begin;
+  const int W = (int)(d.Npad / 32);
+  const int n_rt = (int)((rows + BT::rows - 1) / BT::rows);
+  const int n_ct = (2 * d.M + kTC - 1) / kTC;
+  const int64_t G = (int64_t)n_rt * n_ct * n_seg;
+  const int64_t grid = (G + 8 * BT::round - 1) / (8 * BT::round) * (8 * BT::round);  // whole rounds over 8 XCDs
+  hipLaunchKernelGGL((k_row_pass_split<WR, RING>), dim3((unsigned)grid), dim3(BT::threads), BT::lds, st, d, row_begin,
+                     row_end, n_rt, n_ct, seg_lo, n_seg, bits, W, bits_rows_pad(rows), (float *)T, 2 * seg_stride);
+  return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end, float2 *T,
                                  int64_t seg_stride, const uint32_t *bits, hipStream_t st) {
   (void)S;
-  const int64_t rows = row_end - row_begin;
-  if (rows <= 0) return hipSuccess;
-  const int W = (int)(d.Npad / 32);
+  if (row_end <= row_begin) return hipSuccess;
   int seg_lo, seg_hi;
   split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
   if (seg_hi <= seg_lo) return hipSuccess;
-  const int n_rt = (int)((rows + kTR - 1) / kTR);
-  const int n_ct = (2 * d.M + kTC - 1) / kTC;
-  const int n_seg = seg_hi - seg_lo;
-  const int64_t G = (int64_t)n_rt * n_ct * n_seg;
-  const int64_t grid = (G + 255) / 256 * 256;  // whole rounds of 8 XCDs x 32 slots
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_pass_split, dim3((unsigned)grid), dim3(kThreads), kLdsBytes, st, d, row_begin, row_end,
-                     n_rt, n_ct, seg_lo, n_seg, bits, W, rows, (float *)T, 2 * seg_stride);
-  return hipGetLastError();
+  const int n_seg = seg_hi - seg_lo;
+  if (d.bin_tile_rows == 256) return launch_bin<2, 4>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8) return launch_bin<4, 8>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  return launch_bin<4, 4>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
 }
 
 }  // namespace fzp

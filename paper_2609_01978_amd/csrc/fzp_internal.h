@@ -54,6 +54,8 @@ struct InstDev {
   const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
   int64_t Npad;
   int64_t seg_len;         // split path: K columns per float32 partial sum (power of two)
+  int32_t bin_tile_rows;   // split path, binary stripes: GEMM tile rows (512 or 256)
+  int32_t bin_ring;        // split path, binary stripes, 512-row tile: LDS pipeline stages (4 or 8)
 };
 
 struct InstHost {
@@ -84,6 +86,7 @@ struct Plan {
   std::vector<size_t> off_T, off_bits, off_G;
   int32_t lanes_max = 1, lanes = 1;
   int64_t seg_len = 0;  // split path K segment (all instances)
+  int32_t bin_variant = 2;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;  // [0] fork, [1 + l] join of lane l
   size_t off_scratch, scratch_bytes;

@@ -84,6 +84,15 @@ hipError_t take_events(fzp::Plan &p, hipEvent_t &a, hipEvent_t &b, size_t &first
   return hipSuccess;
 }
 
+// Binary-stripe GEMM variant into every instance's kernel parameters.
+void set_variant(fzp::Plan &p, int32_t v) {
+  p.bin_variant = v;
+  for (auto &ih : p.inst) {
+    ih.dev.bin_tile_rows = v == 1 ? 256 : 512;
+    ih.dev.bin_ring = v == 2 ? 8 : 4;
+  }
+}
+
 }  // namespace
 
 using fzp::InstDev;
@@ -231,7 +240,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     int64_t seg_len = 4096;
     while (seg_len < 65536 && seg_len * 16 <= N) seg_len *= 2;
     p.seg_len = seg_len;
+    p.bin_variant = (o.flags & FZP_FLAG_BIN_TILE_256) ? 1 : ((o.flags & FZP_FLAG_BIN_SHALLOW) ? 0 : 2);
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
+    set_variant(p, p.bin_variant);
     p.lanes_max = o.lanes > 0 ? o.lanes : 1;
     p.lanes = p.lanes_max;
     const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
@@ -715,9 +726,10 @@ extern "C" void fzp_graph_destroy(fzp_graph_t g) { delete g; }
 
 namespace {
 
-void set_seg_len(Plan &p, int64_t seg_len) {
+void set_decomposition(Plan &p, int64_t seg_len, int32_t variant) {
   p.seg_len = seg_len;
   for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
+  set_variant(p, variant);
 }
 
 // Plan shape and device: what the best decomposition depends on.
@@ -736,7 +748,7 @@ std::string tune_key(const Plan &p) {
   return k.str();
 }
 
-bool cache_lookup(const char *path, const std::string &key, int64_t &seg_len, int32_t &lanes) {
+bool cache_lookup(const char *path, const std::string &key, int64_t &seg_len, int32_t &lanes, int32_t &tile) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -745,10 +757,11 @@ bool cache_lookup(const char *path, const std::string &key, int64_t &seg_len, in
     std::istringstream ls(line);
     std::string k;
     int64_t sl;
-    int32_t ln;
-    if (ls >> k >> sl >> ln && k == key) {
+    int32_t ln, tl;
+    if (ls >> k >> sl >> ln >> tl && k == key) {
       seg_len = sl;
       lanes = ln;
+      tile = tl;
       found = true;  // the last entry wins
     }
   }
@@ -759,7 +772,7 @@ bool cache_lookup(const char *path, const std::string &key, int64_t &seg_len, in
 
 extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_dev, void *stream,
                                      const char *cache_path, int64_t *seg_len_out, int32_t *lanes_out,
-                                     double *ms_out) {
+                                     int32_t *variant_out, double *ms_out) {
   if (!h || !workspace || !roi_dev) return fail(FZP_E_INVAL, "fzp_autotune: NULL argument");
   try {
     Plan &p = h->plan;
@@ -767,17 +780,24 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
     const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
     const int64_t seg0 = p.seg_len;
     // candidates: the default segment and its doublings (fewer partial planes,
-    // so they fit the plan's T buffers), and every lane count
+    // so they fit the plan's T buffers), both binary-stripe GEMM tiles, and
+    // every lane count
     std::vector<int64_t> segs{seg0};
-    if (split)
+    std::vector<int32_t> tiles{p.bin_variant};
+    if (split) {
       for (int64_t sl = 2 * seg0; sl <= 65536 && sl < 2 * p.ap.N; sl *= 2) segs.push_back(sl);
+      bool binary = false;
+      for (const auto &ih : p.inst) binary = binary || ih.dev.n_creases == 0;
+      if (binary) tiles = {0, 1, 2};
+    }
     const std::string key = tune_key(p);
     int64_t best_seg = seg0;
-    int32_t best_lanes = p.lanes_max;
+    int32_t best_lanes = p.lanes_max, best_tile = p.bin_variant;
     double best_ms = 0.0;
-    if (cache_lookup(cache_path, key, best_seg, best_lanes) && best_lanes >= 1 && best_lanes <= p.lanes_max &&
-        std::find(segs.begin(), segs.end(), best_seg) != segs.end()) {
-      set_seg_len(p, best_seg);
+    if (cache_lookup(cache_path, key, best_seg, best_lanes, best_tile) && best_lanes >= 1 &&
+        best_lanes <= p.lanes_max && std::find(segs.begin(), segs.end(), best_seg) != segs.end() &&
+        best_tile >= 0 && best_tile <= 2) {
+      set_decomposition(p, best_seg, best_tile);
       p.lanes = best_lanes;
     } else {
       const bool prof = p.profile;
@@ -789,46 +809,51 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
       best_ms = std::numeric_limits<double>::infinity();
       for (int32_t ln = 1; ln <= p.lanes_max && s == FZP_OK; ++ln) {
         for (int64_t sl : segs) {
-          set_seg_len(p, sl);
-          p.lanes = ln;
-          // one untimed run (first use of the lanes, caches), then one timed run
-          s = fzp_propagate_roi(h, workspace, roi_dev, stream);
+          for (int32_t tl : tiles) {
+            set_decomposition(p, sl, tl);
+            p.lanes = ln;
+            // one untimed run (first use of the lanes, caches), then one timed run
+            s = fzp_propagate_roi(h, workspace, roi_dev, stream);
+            if (s != FZP_OK) break;
+            e = hipEventRecord(a, st);
+            if (e != hipSuccess) {
+              s = hip_fail("fzp_autotune: record", e);
+              break;
+            }
+            s = fzp_propagate_roi(h, workspace, roi_dev, stream);
+            if (s != FZP_OK) break;
+            e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+              s = hip_fail("fzp_autotune: timing", e);
+              break;
+            }
+            if (ms < best_ms) {
+              best_ms = ms;
+              best_seg = sl;
+              best_lanes = ln;
+              best_tile = tl;
+            }
+          }
           if (s != FZP_OK) break;
-          e = hipEventRecord(a, st);
-          if (e != hipSuccess) {
-            s = hip_fail("fzp_autotune: record", e);
-            break;
-          }
-          s = fzp_propagate_roi(h, workspace, roi_dev, stream);
-          if (s != FZP_OK) break;
-          e = hipEventRecord(b, st);
-          if (e == hipSuccess) e = hipEventSynchronize(b);
-          float ms = 0.0f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-          if (e != hipSuccess) {
-            s = hip_fail("fzp_autotune: timing", e);
-            break;
-          }
-          if (ms < best_ms) {
-            best_ms = ms;
-            best_seg = sl;
-            best_lanes = ln;
-          }
         }
       }
       if (a) (void)hipEventDestroy(a);
       if (b) (void)hipEventDestroy(b);
       p.profile = prof;
-      set_seg_len(p, best_seg);
+      set_decomposition(p, best_seg, best_tile);
       p.lanes = best_lanes;
       if (s != FZP_OK) return s;
       if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
-        if (f) f << key << " " << best_seg << " " << best_lanes << "\n";
+        if (f) f << key << " " << best_seg << " " << best_lanes << " " << best_tile << "\n";
       }
     }
     if (seg_len_out) *seg_len_out = best_seg;
     if (lanes_out) *lanes_out = best_lanes;
+    if (variant_out) *variant_out = best_tile;
     if (ms_out) *ms_out = best_ms;
     return FZP_OK;
   } catch (const std::exception &ex) {

@@ -134,14 +134,16 @@ def test_split_fzp2mm_vs_fp64_and_oracle():
     assert abs(m["fwhm_x"] / mo["fwhm_x"] - 1) < 1e-3 and abs(m["de"] / mo["de"] - 1) < 1e-3
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("N,M", [(3000, 48), (2500, 128), (4096, 384)])
-def test_split_shapes_ragged(N, M):
-    """Row tiles with a ragged tail, column tiles wider than 2M, several K stages."""
+def test_split_shapes_ragged(N, M, variant):
+    """Row tiles with a ragged tail, column tiles wider than 2M, several K stages,
+    every binary-stripe GEMM variant."""
     ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N)
     inst = dict(lam=LAM0, M=M)
-    announce(f"split N={N} M={M}")
+    announce(f"split N={N} M={M} variant {variant}")
     _, _, _, (U64,) = run_gpu(ap, [inst], allow_undersampled=True)
-    _, _, _, (Us,) = run_gpu(ap, [inst], path="split", allow_undersampled=True)
+    _, _, _, (Us,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, variant=variant)
     a, i = oracle_case(ap, inst)
     ref = O.propagate(a, i, method="bluestein", stripe=512)
     assert rel_l2(O.intensity(U64), O.intensity(ref)) < 1e-9
@@ -208,11 +210,11 @@ def test_split_mixed_instances():
 # Full workload sizes: sampled stripes and properties
 # ---------------------------------------------------------------------------
 
-def _sampled_stripes(name, path, stripes):
+def _sampled_stripes(name, path, stripes, **kw):
     w = workload(name)
     ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
     inst = dict(lam=w["lambda0"], M=w["M"])
-    plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"])
+    plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"], **kw)
     ws, roi = plan.alloc()
     a, i = oracle_case(ap, inst)
     S = w["stripe"]
@@ -245,6 +247,12 @@ def test_fzp1m_sampled_stripes_fp64():
 def test_fzp1m_sampled_stripes_split():
     N = workload("fzp1m")["N"]
     _sampled_stripes("fzp1m", "split", [N // 2 - 64])
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fzp1m_sampled_stripes_split_variants(variant):
+    N = workload("fzp1m")["N"]
+    _sampled_stripes("fzp1m", "split", [N // 2 - 64, 777 * 128], variant=variant)
 
 
 def test_fzp20mm_creased_stripes_split():
