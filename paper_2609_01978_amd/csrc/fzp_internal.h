@@ -89,6 +89,9 @@ struct Plan {
   int32_t bin_variant = 2;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;  // [0] fork, [1 + l] join of lane l
+  std::vector<hipStream_t> aux_st;  // split path: stripe-operand stream of each lane
+  std::vector<hipEvent_t> aux_ev;   // 5 per lane: fork, operand ready x2, GEMM done x2
+  bool capturing = false;           // inside fzp_graph_create's stream capture
   size_t off_scratch, scratch_bytes;
   size_t ws_bytes;
   const void *prepared_ws = nullptr;

@@ -65,6 +65,8 @@ fzp::Plan::~Plan() {
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : lane_ev) (void)hipEventDestroy(e);
   for (hipStream_t t : lane_st) (void)hipStreamDestroy(t);
+  for (hipEvent_t e : aux_ev) (void)hipEventDestroy(e);
+  for (hipStream_t t : aux_st) (void)hipStreamDestroy(t);
 }
 
 namespace {
@@ -313,10 +315,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     for (int l = 0; l < p.lanes_max; ++l) {
       p.off_T.push_back(off);
       off += p.T_bytes;
-      p.off_bits.push_back(off);
-      off += p.bits_bytes;
+      p.off_bits.push_back(off);  // two buffers: chunk c+1's operand is made during chunk c
+      off += 2 * p.bits_bytes;
       p.off_G.push_back(off);
-      off += p.G_bytes;
+      off += 2 * p.G_bytes;
     }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
@@ -460,19 +462,43 @@ hipError_t ensure_lanes(Plan &p) {
   return hipSuccess;
 }
 
+// Auxiliary stream and events of every lane (split path): the stripe operand
+// of chunk c+1 is generated there while the GEMM of chunk c runs.
+hipError_t ensure_aux(Plan &p) {
+  while ((int)p.aux_st.size() < p.lanes_max) {
+    hipStream_t t;
+    hipError_t e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    p.aux_st.push_back(t);
+  }
+  while ((int)p.aux_ev.size() < 5 * p.lanes_max) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    p.aux_ev.push_back(ev);
+  }
+  return hipSuccess;
+}
+
 // Rows [row_begin, row_end) of instance ih into its ROI, on stream st with the
-// stripe buffers of `lane`.
+// stripe buffers of `lane`.  On the split path the stripe operand (mask bits,
+// or the complex stripe planes) of each chunk is generated on the lane's
+// auxiliary stream into one of two buffers, one chunk ahead of the GEMM:
+//   aux:  [wait GEMM(i-1)] stripe(i+1) -> buffer (i+1)%2, record m[(i+1)%2]
+//   st:   wait m[i%2], GEMM(i) <- buffer i%2, record g[i%2], column pass(i)
 fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2 *roi, int64_t row_begin,
                               int64_t row_end, hipStream_t st) {
   const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
   const bool cplx = split && ih.dev.n_creases > 0;
   void *T = ws + p.off_T[lane];
-  uint32_t *bits = (uint32_t *)(ws + p.off_bits[lane]);
-  uint16_t *G = (uint16_t *)(ws + p.off_G[lane]);
   hipError_t e;
-  // chunks are aligned to multiples of chunk_rows from row 0
-  int64_t c0 = row_begin / p.chunk_rows * p.chunk_rows;
-  for (; c0 < row_end; c0 += p.chunk_rows) {
+  // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples
+  struct Chunk {
+    int64_t r0, r1;
+    int nseg;
+  };
+  std::vector<Chunk> chunks;
+  for (int64_t c0 = row_begin / p.chunk_rows * p.chunk_rows; c0 < row_end; c0 += p.chunk_rows) {
     const int64_t r0 = c0 > row_begin ? c0 : row_begin;
     const int64_t r1 = c0 + p.chunk_rows < row_end ? c0 + p.chunk_rows : row_end;
     if (r1 <= r0) continue;
@@ -483,46 +509,89 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
       nseg = sh - sl;
       if (nseg <= 0) continue;  // no disc samples in these rows
     }
-    const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    size_t first = 0;
-    // each launch is bracketed by its own pair of events when profiling
-    auto begin_mark = [&]() -> hipError_t {
-      if (!p.profile) return hipSuccess;
-      hipError_t pe = take_events(p, ea, eb, first);
-      if (pe == hipSuccess) pe = hipEventRecord(ea, st);
-      return pe;
-    };
-    auto end_mark = [&](int kind) -> hipError_t {
-      if (!p.profile) return hipSuccess;
-      hipError_t pe = hipEventRecord(eb, st);
-      p.ev_marks.emplace_back(first, kind);
-      return pe;
-    };
-    if (split) {
-      // the stripe operand: zone-mask bits, or the complex BF16 stripe planes
-      e = begin_mark();
-      if (e == hipSuccess)
-        e = cplx ? fzp::launch_stripe_cplx(ih.dev, r0, r1, G, st) : fzp::launch_mask_bits(ih.dev, r0, r1, bits, st);
-      if (e == hipSuccess) e = end_mark(2);
+    chunks.push_back({r0, r1, nseg});
+  }
+  if (chunks.empty()) return FZP_OK;
+  const int64_t seg_stride = p.chunk_rows * (int64_t)ih.dev.M;
+  // each launch is bracketed by its own pair of events when profiling
+  hipEvent_t ea = nullptr, eb = nullptr;
+  size_t first = 0;
+  auto begin_mark = [&](hipStream_t s) -> hipError_t {
+    if (!p.profile) return hipSuccess;
+    hipError_t pe = take_events(p, ea, eb, first);
+    if (pe == hipSuccess) pe = hipEventRecord(ea, s);
+    return pe;
+  };
+  auto end_mark = [&](int kind, hipStream_t s) -> hipError_t {
+    if (!p.profile) return hipSuccess;
+    hipError_t pe = hipEventRecord(eb, s);
+    p.ev_marks.emplace_back(first, kind);
+    return pe;
+  };
+  // Under graph capture the operand is made on st itself (no auxiliary
+  // stream), one chunk at a time.
+  const bool overlap = split && !p.capturing;
+  hipStream_t ax = st;
+  hipEvent_t *ev = nullptr;  // [0] fork, [1 + b] stripe b ready, [3 + b] GEMM done with buffer b
+  auto stripe = [&](size_t i) -> hipError_t {
+    const int b = (int)(i % 2);
+    hipError_t pe = hipSuccess;
+    if (overlap && i >= 2) pe = hipStreamWaitEvent(ax, ev[3 + b], 0);
+    if (pe == hipSuccess) pe = begin_mark(ax);
+    if (pe == hipSuccess)
+      pe = cplx ? fzp::launch_stripe_cplx(ih.dev, chunks[i].r0, chunks[i].r1,
+                                          (uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), ax)
+                : fzp::launch_mask_bits(ih.dev, chunks[i].r0, chunks[i].r1,
+                                        (uint32_t *)(ws + p.off_bits[lane] + b * p.bits_bytes), ax);
+    if (pe == hipSuccess) pe = end_mark(2, ax);
+    if (pe == hipSuccess && overlap) pe = hipEventRecord(ev[1 + b], ax);
+    return pe;
+  };
+  if (overlap) {
+    e = ensure_aux(p);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: auxiliary stream", e);
+    ax = p.aux_st[lane];
+    ev = &p.aux_ev[5 * lane];
+    // fork: the auxiliary stream starts after the work already on st
+    e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ax, ev[0], 0);
+    if (e == hipSuccess) e = stripe(0);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
+  } else if (split) {
+    e = stripe(0);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
+  }
+  for (size_t i = 0; i < chunks.size(); ++i) {
+    const int64_t r0 = chunks[i].r0, r1 = chunks[i].r1;
+    const int b = (int)(i % 2);
+    if (overlap) {
+      e = i + 1 < chunks.size() ? stripe(i + 1) : hipSuccess;
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[1 + b], 0);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
+    } else if (split && i > 0) {
+      e = stripe(i);
       if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: stripe operand", e);
     }
-    e = begin_mark();
+    e = begin_mark(st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
     if (cplx)
-      e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride, G, st);
+      e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride,
+                                          (const uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), st);
     else if (split)
-      e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, bits, st);
+      e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride,
+                                     (const uint32_t *)(ws + p.off_bits[lane] + b * p.bits_bytes), st);
     else
       e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
-    e = end_mark(0);
-    if (e == hipSuccess) e = begin_mark();
+    e = end_mark(0, st);
+    if (e == hipSuccess && overlap) e = hipEventRecord(ev[3 + b], st);
+    if (e == hipSuccess) e = begin_mark(st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-    e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, nseg, seg_stride, roi, st);
-    if (e == hipSuccess) e = end_mark(1);
+    e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, chunks[i].nseg, seg_stride, roi, st);
+    if (e == hipSuccess) e = end_mark(1, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
   }
+  // every stripe launch on the auxiliary stream was waited for by st
   return FZP_OK;
 }
 
@@ -689,7 +758,9 @@ extern "C" fzp_status_t fzp_graph_create(fzp_plan_t h, void *workspace, double *
   p.profile = false;
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    p.capturing = true;
     s = fzp_propagate_roi_range(h, workspace, roi_dev, 0, p.ap.N, 0, cs);
+    p.capturing = false;
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &graph);
     g->graph = graph;
