@@ -94,7 +94,12 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
     rlo = (Nm1 - m + 1) >> 1;
     rhi = ((Nm1 + m) >> 1) + 1;
   }
-  const int w0 = blockIdx.y * 64, w1 = min(w0 + 64, W);
+  // With N = 32 W, columns i and N-1-i (offsets c and -c) have the same K and
+  // the chord is symmetric, so word W-1-w is word w bit-reversed: only the
+  // left half of the words is evaluated.
+  const bool mirror = (int64_t)32 * W == N;
+  const int wend = mirror ? W / 2 : W;
+  const int w0 = blockIdx.y * 64, w1 = min(w0 + 64, wend);
   for (int w = w0; w < w1; ++w) {
     const int i0 = 32 * w;
     uint32_t v = 0;
@@ -112,6 +117,7 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
       v = (v ^ flip) & valid;
     }
     bits[(int64_t)w * rows_pad + rl] = v;
+    if (mirror) bits[(int64_t)(W - 1 - w) * rows_pad + rl] = __builtin_bitreverse32(v);
   }
 }
 
@@ -152,7 +158,7 @@ constexpr int kRing = 4, kAhead = 3;
 // work-group's barrier and pipeline start-up are covered by the other's
 // MFMAs).  Each wave copies 8 / WR slab pieces and one mask-word piece per
 // stage.
-template <int WR, int RING = kRing> struct BinTile {
+template <int WR, int RING = kRing, bool PF = false> struct BinTile {
   static constexpr int rows = 128 * WR;
   static constexpr int threads = 128 * WR;
   static constexpr int waves = 2 * WR;
@@ -165,16 +171,18 @@ template <int WR, int RING = kRing> struct BinTile {
   static constexpr int lds = RING * (kBBytes + bits_bytes);
   static constexpr int round = 32 * per_cu;               // concurrent work-groups per XCD
   // copies a wave may leave outstanding at the end of a stage: those of the
-  // RING - 2 stages after the next one
-  static constexpr int wait = (RING - 2) * copies;
+  // RING - 2 stages after the next one; with PF (fragments of the next stage
+  // read one stage early) the stage after the next must be complete as well
+  static constexpr int wait = (RING - (PF ? 3 : 2)) * copies;
 };
 
 // s_waitcnt vmcnt(N) + s_barrier for the outstanding-copy counts used above.
 template <int N> __device__ __forceinline__ void wait_barrier() {
-  static_assert(N == 6 || N == 10 || N == 12 || N == 18 || N == 20, "add the count");
+  static_assert(N == 6 || N == 10 || N == 12 || N == 15 || N == 18 || N == 20, "add the count");
   if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 10) asm volatile("s_waitcnt vmcnt(10) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 12) asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 15) asm volatile("s_waitcnt vmcnt(15) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 18) asm volatile("s_waitcnt vmcnt(18) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   if constexpr (N == 20) asm volatile("s_waitcnt vmcnt(20) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -225,14 +233,14 @@ __device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t
   hi = (hi2 / 2 < N - 1 ? hi2 / 2 : N - 1) + 1;
 }
 
-template <int WR, int RING>
+template <int WR, int RING, bool PF>
 __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
                                                                 int n_rt, int n_ct, int seg_lo, int n_seg,
                                                                 const uint32_t *__restrict__ bits, int W,
                                                                 int64_t bits_rows, float *__restrict__ T,
                                                                 int64_t seg_stride_f) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  using BT = BinTile<WR, RING>;
+  using BT = BinTile<WR, RING, PF>;
   constexpr int kTR = BT::rows;
   constexpr int kBitsBytes = BT::bits_bytes;
   constexpr int kRing = BT::ring, kAhead = BT::ahead;
@@ -325,38 +333,70 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
     };
     for (int s = 0; s < kAhead; ++s) copy_stage(s);
     wait_barrier<BT::wait>();
-    for (int s = 0; s < nst; ++s) {
-      copy_stage(s + kAhead);
-      const char *sb = bbuf + (s % kRing) * kBBytes + brow;
+    // operand fragments: words of the stage, B chunks (hi, lo) of a K-step
+    auto load_words = [&](int s, uint32_t (&word)[4]) {
       const uint32_t *sw = (const uint32_t *)(wbuf + (s % kRing) * kBitsBytes) + wr * 128 + l32;
-      uint32_t word[4];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) word[rb] = sw[rb * 32];
+    };
+    auto load_b = [&](int s, int ks, bf16x8 (&bh)[2], bf16x8 (&bl)[2]) {
+      const char *sb = bbuf + (s % kRing) * kBBytes + brow;
+      const int cofs = ks ? cks1 : cks0;
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const int cofs = ks ? cks1 : cks0;
-        bf16x8 bh[2], bl[2], a[4];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + cb * 32 * kRowB + cofs));
-          bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + (kTC + cb * 32) * kRowB + cofs));
-        }
-        // byte (2 ks + lhi) of the row word holds this lane's 8 columns of K-step ks
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) a[rb] = expand8((word[rb] >> (8 * (2 * ks + lhi))) & 0xffu);
-        // 8 independent accumulators per operand plane: consecutive MFMAs never wait on each other
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bh[cb], acc[rb][cb], 0, 0, 0);
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+      for (int cb = 0; cb < 2; ++cb) {
+        bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + cb * 32 * kRowB + cofs));
+        bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + (kTC + cb * 32) * kRowB + cofs));
       }
-      wait_barrier<BT::wait>();
+    };
+    // one K-step: byte (2 ks + lhi) of each row word holds this lane's 8 columns;
+    // 8 independent accumulators per operand plane, so consecutive MFMAs never
+    // wait on each other
+    auto ksteps = [&](const uint32_t (&word)[4], int ks, const bf16x8 (&bh)[2], const bf16x8 (&bl)[2]) {
+      bf16x8 a[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) a[rb] = expand8((word[rb] >> (8 * (2 * ks + lhi))) & 0xffu);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bh[cb], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+    };
+    if constexpr (!PF) {
+      for (int s = 0; s < nst; ++s) {
+        copy_stage(s + kAhead);
+        uint32_t word[4];
+        load_words(s, word);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          bf16x8 bh[2], bl[2];
+          load_b(s, ks, bh, bl);
+          ksteps(word, ks, bh, bl);
+        }
+        wait_barrier<BT::wait>();
+      }
+    } else {
+      // The first K-step's fragments of stage s + 1 are read during stage s
+      // (that stage is complete and visible since the barrier ending s - 1).
+      uint32_t word[4], nword[4];
+      bf16x8 bh0[2], bl0[2], bh1[2], bl1[2];
+      load_words(0, word);
+      load_b(0, 0, bh0, bl0);
+      for (int s = 0; s < nst; ++s) {
+        copy_stage(s + kAhead);
+        load_b(s, 1, bh1, bl1);
+        ksteps(word, 0, bh0, bl0);
+        load_words(s + 1, nword);
+        load_b(s + 1, 0, bh0, bl0);
+        ksteps(word, 1, bh1, bl1);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) word[rb] = nword[rb];
+        wait_barrier<BT::wait>();
+      }
     }
     // drain the copies still in flight before the work-group retires its LDS
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -635,13 +675,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, 
 hipError_t init_split_attributes() {
   static bool done = false;  // set once per process (the attributes are per function)
   if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 4>::lds);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<4, 8>::lds);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            BinTile<4, 8, true>::lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<2, 4>::lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -709,23 +752,24 @@ hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end
   if (rows <= 0) return hipSuccess;
   const int W = (int)(d.Npad / 32);
   const int64_t rows_pad = bits_rows_pad(rows);
-  const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)((W + 63) / 64));
+  const int wend = (int64_t)32 * W == d.N ? W / 2 : W;  // mirrored halves (see k_mask_bits)
+  const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)((wend + 63) / 64));
   hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, W, bits);
   return hipGetLastError();
 }
 
 namespace {
-template <int WR, int RING>
+template <int WR, int RING, bool PF>
 hipError_t launch_bin(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
                       const uint32_t *bits, int seg_lo, int n_seg, hipStream_t st) {
-  using BT = BinTile<WR, RING>;
+  using BT = BinTile<WR, RING, PF>;
   const int64_t rows = row_end - row_begin;
   const int W = (int)(d.Npad / 32);
   const int n_rt = (int)((rows + BT::rows - 1) / BT::rows);
   const int n_ct = (2 * d.M + kTC - 1) / kTC;
   const int64_t G = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (G + 8 * BT::round - 1) / (8 * BT::round) * (8 * BT::round);  // whole rounds over 8 XCDs
-  hipLaunchKernelGGL((k_row_pass_split<WR, RING>), dim3((unsigned)grid), dim3(BT::threads), BT::lds, st, d, row_begin,
+  hipLaunchKernelGGL((k_row_pass_split<WR, RING, PF>), dim3((unsigned)grid), dim3(BT::threads), BT::lds, st, d, row_begin,
                      row_end, n_rt, n_ct, seg_lo, n_seg, bits, W, bits_rows_pad(rows), (float *)T, 2 * seg_stride);
   return hipGetLastError();
 }
@@ -741,9 +785,12 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
   const int n_seg = seg_hi - seg_lo;
-  if (d.bin_tile_rows == 256) return launch_bin<2, 4>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-  if (d.bin_ring == 8) return launch_bin<4, 8>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-  return launch_bin<4, 4>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_tile_rows == 256)
+    return launch_bin<2, 4, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8 && d.bin_prefetch)
+    return launch_bin<4, 8, true>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8) return launch_bin<4, 8, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  return launch_bin<4, 4, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
 }
 
 }  // namespace fzp

@@ -91,7 +91,8 @@ void set_variant(fzp::Plan &p, int32_t v) {
   p.bin_variant = v;
   for (auto &ih : p.inst) {
     ih.dev.bin_tile_rows = v == 1 ? 256 : 512;
-    ih.dev.bin_ring = v == 2 ? 8 : 4;
+    ih.dev.bin_ring = v >= 2 ? 8 : 4;
+    ih.dev.bin_prefetch = v == 3 ? 1 : 0;
   }
 }
 
@@ -242,7 +243,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     int64_t seg_len = 4096;
     while (seg_len < 65536 && seg_len * 16 <= N) seg_len *= 2;
     p.seg_len = seg_len;
-    p.bin_variant = (o.flags & FZP_FLAG_BIN_TILE_256) ? 1 : ((o.flags & FZP_FLAG_BIN_SHALLOW) ? 0 : 2);
+    p.bin_variant = (o.flags & FZP_FLAG_BIN_TILE_256) ? 1
+                    : (o.flags & FZP_FLAG_BIN_SHALLOW) ? 0
+                    : (o.flags & FZP_FLAG_BIN_PREFETCH) ? 3 : 2;
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
     set_variant(p, p.bin_variant);
     p.lanes_max = o.lanes > 0 ? o.lanes : 1;
@@ -315,10 +318,12 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     for (int l = 0; l < p.lanes_max; ++l) {
       p.off_T.push_back(off);
       off += p.T_bytes;
-      p.off_bits.push_back(off);  // two buffers: chunk c+1's operand is made during chunk c
-      off += 2 * p.bits_bytes;
+      // two operand buffers when chunk c+1's operand is made during chunk c
+      const size_t nbuf = (o.flags & FZP_FLAG_OVERLAP_OPERAND) ? 2 : 1;
+      p.off_bits.push_back(off);
+      off += nbuf * p.bits_bytes;
       p.off_G.push_back(off);
-      off += 2 * p.G_bytes;
+      off += nbuf * p.G_bytes;
     }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
@@ -528,13 +533,13 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     p.ev_marks.emplace_back(first, kind);
     return pe;
   };
-  // Under graph capture the operand is made on st itself (no auxiliary
-  // stream), one chunk at a time.
-  const bool overlap = split && !p.capturing;
+  // Without FZP_FLAG_OVERLAP_OPERAND, and always under graph capture, the
+  // operand is made on st itself, one chunk at a time.
+  const bool overlap = split && !p.capturing && (p.opt.flags & FZP_FLAG_OVERLAP_OPERAND);
   hipStream_t ax = st;
   hipEvent_t *ev = nullptr;  // [0] fork, [1 + b] stripe b ready, [3 + b] GEMM done with buffer b
   auto stripe = [&](size_t i) -> hipError_t {
-    const int b = (int)(i % 2);
+    const int b = overlap ? (int)(i % 2) : 0;
     hipError_t pe = hipSuccess;
     if (overlap && i >= 2) pe = hipStreamWaitEvent(ax, ev[3 + b], 0);
     if (pe == hipSuccess) pe = begin_mark(ax);
@@ -563,7 +568,7 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
   }
   for (size_t i = 0; i < chunks.size(); ++i) {
     const int64_t r0 = chunks[i].r0, r1 = chunks[i].r1;
-    const int b = (int)(i % 2);
+    const int b = overlap ? (int)(i % 2) : 0;
     if (overlap) {
       e = i + 1 < chunks.size() ? stripe(i + 1) : hipSuccess;
       if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[1 + b], 0);
@@ -859,7 +864,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
       for (int64_t sl = 2 * seg0; sl <= 65536 && sl < 2 * p.ap.N; sl *= 2) segs.push_back(sl);
       bool binary = false;
       for (const auto &ih : p.inst) binary = binary || ih.dev.n_creases == 0;
-      if (binary) tiles = {0, 1, 2};
+      if (binary) tiles = {0, 1, 2, 3};
     }
     const std::string key = tune_key(p);
     int64_t best_seg = seg0;
@@ -867,7 +872,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
     double best_ms = 0.0;
     if (cache_lookup(cache_path, key, best_seg, best_lanes, best_tile) && best_lanes >= 1 &&
         best_lanes <= p.lanes_max && std::find(segs.begin(), segs.end(), best_seg) != segs.end() &&
-        best_tile >= 0 && best_tile <= 2) {
+        best_tile >= 0 && best_tile <= 3) {
       set_decomposition(p, best_seg, best_tile);
       p.lanes = best_lanes;
     } else {
