@@ -351,10 +351,11 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
     // one K-step: byte (2 ks + lhi) of each row word holds this lane's 8 columns;
     // 8 independent accumulators per operand plane, so consecutive MFMAs never
     // wait on each other
-    auto ksteps = [&](const uint32_t (&word)[4], int ks, const bf16x8 (&bh)[2], const bf16x8 (&bl)[2]) {
-      bf16x8 a[4];
+    auto expand = [&](const uint32_t (&word)[4], int ks, bf16x8 (&a)[4]) {
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) a[rb] = expand8((word[rb] >> (8 * (2 * ks + lhi))) & 0xffu);
+    };
+    auto mfmas = [&](const bf16x8 (&a)[4], const bf16x8 (&bh)[2], const bf16x8 (&bl)[2]) {
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -373,26 +374,33 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
         load_words(s, word);
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          bf16x8 bh[2], bl[2];
+          bf16x8 bh[2], bl[2], a[4];
           load_b(s, ks, bh, bl);
-          ksteps(word, ks, bh, bl);
+          expand(word, ks, a);
+          mfmas(a, bh, bl);
         }
         wait_barrier<BT::wait>();
       }
     } else {
-      // The first K-step's fragments of stage s + 1 are read during stage s
-      // (that stage is complete and visible since the barrier ending s - 1).
+      // Software pipelined across the stage barrier: the first K-step's
+      // operands of stage s + 1 (mask words expanded, table fragments) are
+      // prepared during stage s, which is possible because stage s + 1 is
+      // complete and visible since the barrier that ended stage s - 1.  After
+      // each barrier the MFMAs start at once.
       uint32_t word[4], nword[4];
-      bf16x8 bh0[2], bl0[2], bh1[2], bl1[2];
+      bf16x8 a0[4], a1[4], bh0[2], bl0[2], bh1[2], bl1[2];
       load_words(0, word);
       load_b(0, 0, bh0, bl0);
+      expand(word, 0, a0);
       for (int s = 0; s < nst; ++s) {
         copy_stage(s + kAhead);
         load_b(s, 1, bh1, bl1);
-        ksteps(word, 0, bh0, bl0);
+        mfmas(a0, bh0, bl0);
+        expand(word, 1, a1);
         load_words(s + 1, nword);
         load_b(s + 1, 0, bh0, bl0);
-        ksteps(word, 1, bh1, bl1);
+        mfmas(a1, bh1, bl1);
+        expand(nword, 0, a0);
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) word[rb] = nword[rb];
         wait_barrier<BT::wait>();
