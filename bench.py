@@ -54,6 +54,22 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
+def committed_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(here, summary)).read()
+        src = open(os.path.join(here, kernel_src), "rb").read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("|", "#")))
+    if vals.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def bluestein_blocks(N: int, B: int) -> int:
     """Blocks of B samples covering every aperture row's disc chord (row pass)."""
     import numpy as np
@@ -213,8 +229,11 @@ def main():
     row_ms_step = pr["row_ms"] / max(args.steps, 1)
     flops_step = 8.0 * M * disc
     achieved = flops_step / (row_ms_step * 1e-3) / 1e12
+    traffic = committed_traffic("paper_2609_01978_amd/csrc/fzp_gemm.hip",
+                                "profiles/hbm_traffic_k_row_pass_split_fzp1m.md") if args.workload == "fzp1m" else None
     roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
+                    traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     kernel="k_row_pass_split",
                     launch_ms=round(pr["row_ms"] / max(pr["row_launches"], 1), 3),
                     launches_per_step=launches_per_step,
