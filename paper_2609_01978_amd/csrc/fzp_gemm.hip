@@ -474,28 +474,53 @@ __global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begi
   const int64_t plane = nkb * rows_pad * 16;
   for (int64_t kb = blockIdx.y; kb < nkb; kb += gridDim.y) {
     const int64_t i0 = 16 * (kb0 + kb);
+    const double c0 = (double)(2 * i0 - N + 1);
+    // zone mask of the 16 samples (exact integer rule)
+    uint32_t open = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const double ci = c0 + 2.0 * e;
+      const double K = fma(ci, ci, bj);
+      const int zone = (int)(K * d.kappa);
+      const bool o = live && i0 + e < N && K <= d.kmax && (((zone & 1) ^ d.centre_open) != 0);
+      open |= (o ? 1u : 0u) << e;
+    }
+    // Crease phase in turns.  Along the row the ridge distance d grows by
+    // st = dx cos(theta) per sample, so the Gaussian g = exp(-a d^2) obeys
+    // g(i+1) = g(i) r(i) with r(i+1) = r(i) q, r(0) = exp(-a (2 d0 st + st^2)),
+    // q = exp(-2 a st^2): three exponentials per ridge per 16 samples, started
+    // from the float64 distance of the first sample.
+    float turns[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) turns[e] = 0.0f;
+    const double x0 = hdx * c0;
+    for (int k = 0; k < nc; ++k) {
+      const float dd = (float)fma(x0, cr[k].c, fma(y, cr[k].s, -cr[k].rho));
+      const float st = (float)(d.dx * cr[k].c);
+      const float a = (float)cr[k].inv2s2;
+      const float h = (float)cr[k].h_over_lambda;
+      float g = __expf(-a * dd * dd);
+      float r = __expf(-a * (2.0f * dd * st + st * st));
+      const float q = __expf(-2.0f * a * st * st);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        turns[e] = fmaf(h, g, turns[e]);
+        g *= r;
+        r *= q;
+      }
+    }
     uint32_t w[4][8];
 #pragma unroll
     for (int e = 0; e < 16; e += 2) {
       uint32_t pr[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int64_t i = i0 + e + u;
-        const double ci = (double)(2 * i - N + 1);
-        const double K = fma(ci, ci, bj);
-        const int zone = (int)(K * d.kappa);
-        const bool open = live && i < N && K <= d.kmax && (((zone & 1) ^ d.centre_open) != 0);
-        const double x = hdx * ci;
-        float turns = 0.0f;
-        for (int k = 0; k < nc; ++k) {
-          const double dd = fma(x, cr[k].c, fma(y, cr[k].s, -cr[k].rho));
-          const float df = (float)dd;
-          turns += (float)cr[k].h_over_lambda * __expf(-df * df * (float)cr[k].inv2s2);
-        }
-        turns -= rintf(turns);
+        float t = turns[e + u];
+        t -= rintf(t);
         float sn, cs;
-        sincospif(2.0f * turns, &sn, &cs);
-        const float gr = open ? cs : 0.0f, gi = open ? sn : 0.0f;
+        sincospif(2.0f * t, &sn, &cs);
+        const bool o = (open >> (e + u)) & 1u;
+        const float gr = o ? cs : 0.0f, gi = o ? sn : 0.0f;
         const uint16_t rh = bf16_rne(gr), ih = bf16_rne(gi);
         const uint16_t rlo = bf16_rne(gr - __uint_as_float((uint32_t)rh << 16));
         const uint16_t ilo = bf16_rne(gi - __uint_as_float((uint32_t)ih << 16));
