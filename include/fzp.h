@@ -69,12 +69,14 @@ typedef int32_t fzp_status_t;
 /* Plan flags. */
 #define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */
 /* Split path, binary stripes: the GEMM variant a plan starts with (fzp_autotune may
- * change it).  Without either flag: variant 2, the 512-row tile (one work-group per
- * compute unit) with an 8-stage LDS pipeline. */
+ * change it).  Without a variant flag: variant 4, the 512-row tile (one work-group per
+ * compute unit) with an 8-stage LDS pipeline and the mask expansion interleaved with
+ * the MFMAs. */
 #define FZP_FLAG_BIN_TILE_256 2       /* variant 1: 256-row tile, two work-groups per compute unit */
 #define FZP_FLAG_BIN_SHALLOW 4        /* variant 0: 512-row tile with a 4-stage LDS pipeline */
 #define FZP_FLAG_BIN_PREFETCH 8       /* variant 3: variant 2 reading the next stage's first
                                          operand fragments one stage early */
+#define FZP_FLAG_BIN_DEEP 32          /* variant 2: 512-row tile with an 8-stage LDS pipeline */
 #define FZP_FLAG_OVERLAP_OPERAND 16   /* split path: make each chunk's stripe operand on an internal
                                          auxiliary stream one chunk ahead of its GEMM (two operand
                                          buffers; not inside fzp_graph_create's capture) */
@@ -207,7 +209,8 @@ void fzp_graph_destroy(fzp_graph_t g);
  * (0: 512-row tile, one work-group per compute unit, 4-stage LDS pipeline;
  * 1: 256-row tile, two work-groups per compute unit; 2: 512-row tile with an
  * 8-stage pipeline; 3: variant 2 with the next stage's first operand fragments
- * read one stage early), and the number of concurrent lanes (1 .. options.lanes).  Each candidate runs one
+ * read one stage early; 4: variant 2 with the mask expansion interleaved with the
+ * MFMAs), and the number of concurrent lanes (1 .. options.lanes).  Each candidate runs one
  * full propagation on `stream`, timed with HIP events; the fastest is kept in
  * the plan.  With a non-NULL `cache_path` the choice is looked up first in
  * that text file (one "key seg_len lanes variant" line per plan shape and

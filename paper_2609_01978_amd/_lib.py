@@ -33,6 +33,7 @@ FLAG_BIN_TILE_256 = 2
 FLAG_BIN_SHALLOW = 4
 FLAG_BIN_PREFETCH = 8
 FLAG_OVERLAP_OPERAND = 16
+FLAG_BIN_DEEP = 32
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
@@ -179,7 +180,7 @@ class Plan:
 
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
                  chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
-                 lanes: int = 0, variant: int = 2, overlap_operand: bool = False):
+                 lanes: int = 0, variant: int = 4, overlap_operand: bool = False):
         lib = load_library()
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
@@ -201,7 +202,8 @@ class Plan:
         p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16}[path] if isinstance(path, str) else int(path)
         opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
                       flags=(FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0)
-                      | {0: FLAG_BIN_SHALLOW, 1: FLAG_BIN_TILE_256, 2: 0, 3: FLAG_BIN_PREFETCH}[variant]
+                      | {0: FLAG_BIN_SHALLOW, 1: FLAG_BIN_TILE_256, 2: FLAG_BIN_DEEP,
+                         3: FLAG_BIN_PREFETCH, 4: 0}[variant]
                       | (FLAG_OVERLAP_OPERAND if overlap_operand else 0), lanes=int(lanes))
         h = ctypes.c_void_p()
         _check(lib, lib.fzp_plan(ctypes.byref(ap), arr, n, ctypes.byref(opt), ctypes.byref(h)))

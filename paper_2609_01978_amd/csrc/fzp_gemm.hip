@@ -158,7 +158,7 @@ constexpr int kRing = 4, kAhead = 3;
 // work-group's barrier and pipeline start-up are covered by the other's
 // MFMAs).  Each wave copies 8 / WR slab pieces and one mask-word piece per
 // stage.
-template <int WR, int RING = kRing, bool PF = false> struct BinTile {
+template <int WR, int RING = kRing, bool PF = false, bool IL = false> struct BinTile {
   static constexpr int rows = 128 * WR;
   static constexpr int threads = 128 * WR;
   static constexpr int waves = 2 * WR;
@@ -233,14 +233,14 @@ __device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t
   hi = (hi2 / 2 < N - 1 ? hi2 / 2 : N - 1) + 1;
 }
 
-template <int WR, int RING, bool PF>
+template <int WR, int RING, bool PF, bool IL>
 __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
                                                                 int n_rt, int n_ct, int seg_lo, int n_seg,
                                                                 const uint32_t *__restrict__ bits, int W,
                                                                 int64_t bits_rows, float *__restrict__ T,
                                                                 int64_t seg_stride_f) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  using BT = BinTile<WR, RING, PF>;
+  using BT = BinTile<WR, RING, PF, IL>;
   constexpr int kTR = BT::rows;
   constexpr int kBitsBytes = BT::bits_bytes;
   constexpr int kRing = BT::ring, kAhead = BT::ahead;
@@ -367,6 +367,27 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
         for (int cb = 0; cb < 2; ++cb)
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
     };
+    // Interleaved K-step: the mask operand of row block rb + 1 is expanded
+    // while the MFMAs of row block rb run (scheduling fences keep VALU and
+    // MFMA in this order; LDS reads and scalar work may still move).
+    auto kstep_il = [&](const uint32_t (&word)[4], int ks, const bf16x8 (&bh)[2], const bf16x8 (&bl)[2]) {
+      bf16x8 a[4];
+      const int sh = 8 * (2 * ks + lhi);
+      a[0] = expand8((word[0] >> sh) & 0xffu);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        __builtin_amdgcn_sched_barrier(0x0104);
+        acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bh[0], acc[rb][0], 0, 0, 0);
+        acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bh[1], acc[rb][1], 0, 0, 0);
+        if (rb < 3) a[rb + 1] = expand8((word[rb + 1] >> sh) & 0xffu);
+      }
+      __builtin_amdgcn_sched_barrier(0x0104);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], bl[cb], acc[rb][cb], 0, 0, 0);
+    };
     if constexpr (!PF) {
       for (int s = 0; s < nst; ++s) {
         copy_stage(s + kAhead);
@@ -376,8 +397,12 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
         for (int ks = 0; ks < 2; ++ks) {
           bf16x8 bh[2], bl[2], a[4];
           load_b(s, ks, bh, bl);
-          expand(word, ks, a);
-          mfmas(a, bh, bl);
+          if constexpr (IL) {
+            kstep_il(word, ks, bh, bl);
+          } else {
+            expand(word, ks, a);
+            mfmas(a, bh, bl);
+          }
         }
         wait_barrier<BT::wait>();
       }
@@ -708,16 +733,19 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, 
 hipError_t init_split_attributes() {
   static bool done = false;  // set once per process (the attributes are per function)
   if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4, false>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4, false, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 4>::lds);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<4, 8>::lds);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            BinTile<4, 8, true>::lds);
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, true, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 8, true>::lds);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 8, false, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 8>::lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<2, 4>::lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -792,17 +820,17 @@ hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end
 }
 
 namespace {
-template <int WR, int RING, bool PF>
+template <int WR, int RING, bool PF, bool IL>
 hipError_t launch_bin(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
                       const uint32_t *bits, int seg_lo, int n_seg, hipStream_t st) {
-  using BT = BinTile<WR, RING, PF>;
+  using BT = BinTile<WR, RING, PF, IL>;
   const int64_t rows = row_end - row_begin;
   const int W = (int)(d.Npad / 32);
   const int n_rt = (int)((rows + BT::rows - 1) / BT::rows);
   const int n_ct = (2 * d.M + kTC - 1) / kTC;
   const int64_t G = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (G + 8 * BT::round - 1) / (8 * BT::round) * (8 * BT::round);  // whole rounds over 8 XCDs
-  hipLaunchKernelGGL((k_row_pass_split<WR, RING, PF>), dim3((unsigned)grid), dim3(BT::threads), BT::lds, st, d, row_begin,
+  hipLaunchKernelGGL((k_row_pass_split<WR, RING, PF, IL>), dim3((unsigned)grid), dim3(BT::threads), BT::lds, st, d, row_begin,
                      row_end, n_rt, n_ct, seg_lo, n_seg, bits, W, bits_rows_pad(rows), (float *)T, 2 * seg_stride);
   return hipGetLastError();
 }
@@ -819,11 +847,14 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   if (e != hipSuccess) return e;
   const int n_seg = seg_hi - seg_lo;
   if (d.bin_tile_rows == 256)
-    return launch_bin<2, 4, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-  if (d.bin_ring == 8 && d.bin_prefetch)
-    return launch_bin<4, 8, true>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-  if (d.bin_ring == 8) return launch_bin<4, 8, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-  return launch_bin<4, 4, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+    return launch_bin<2, 4, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8 && d.bin_prefetch == 1)
+    return launch_bin<4, 8, true, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8 && d.bin_prefetch == 2)
+    return launch_bin<4, 8, false, true>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  if (d.bin_ring == 8)
+    return launch_bin<4, 8, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
+  return launch_bin<4, 4, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
 }
 
 }  // namespace fzp

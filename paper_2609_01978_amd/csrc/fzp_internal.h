@@ -56,7 +56,7 @@ struct InstDev {
   int64_t seg_len;         // split path: K columns per float32 partial sum (power of two)
   int32_t bin_tile_rows;   // split path, binary stripes: GEMM tile rows (512 or 256)
   int32_t bin_ring;        // split path, binary stripes, 512-row tile: LDS pipeline stages (4 or 8)
-  int32_t bin_prefetch;    // 8-stage variant: read the next stage's first fragments one stage early
+  int32_t bin_prefetch;    // 8-stage variant: 1 next-stage operands one stage early, 2 interleaved expansion
   int32_t pad_;
 };
 
@@ -88,8 +88,8 @@ struct Plan {
   std::vector<size_t> off_T, off_bits, off_G;
   int32_t lanes_max = 1, lanes = 1;
   int64_t seg_len = 0;  // split path K segment (all instances)
-  int32_t bin_variant = 2;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring,
-                            // 3 deep ring with next-stage fragment prefetch
+  int32_t bin_variant = 4;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring,
+                            // 3 deep ring with next-stage fragment prefetch, 4 deep ring interleaved
   std::vector<hipStream_t> lane_st;
   std::vector<hipEvent_t> lane_ev;  // [0] fork, [1 + l] join of lane l
   std::vector<hipStream_t> aux_st;  // split path: stripe-operand stream of each lane

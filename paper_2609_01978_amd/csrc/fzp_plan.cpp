@@ -92,7 +92,7 @@ void set_variant(fzp::Plan &p, int32_t v) {
   for (auto &ih : p.inst) {
     ih.dev.bin_tile_rows = v == 1 ? 256 : 512;
     ih.dev.bin_ring = v >= 2 ? 8 : 4;
-    ih.dev.bin_prefetch = v == 3 ? 1 : 0;
+    ih.dev.bin_prefetch = v == 3 ? 1 : (v == 4 ? 2 : 0);
   }
 }
 
@@ -245,7 +245,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     p.seg_len = seg_len;
     p.bin_variant = (o.flags & FZP_FLAG_BIN_TILE_256) ? 1
                     : (o.flags & FZP_FLAG_BIN_SHALLOW) ? 0
-                    : (o.flags & FZP_FLAG_BIN_PREFETCH) ? 3 : 2;
+                    : (o.flags & FZP_FLAG_BIN_PREFETCH) ? 3
+                    : (o.flags & FZP_FLAG_BIN_DEEP) ? 2 : 4;
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
     set_variant(p, p.bin_variant);
     p.lanes_max = o.lanes > 0 ? o.lanes : 1;
@@ -864,7 +865,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
       for (int64_t sl = 2 * seg0; sl <= 65536 && sl < 2 * p.ap.N; sl *= 2) segs.push_back(sl);
       bool binary = false;
       for (const auto &ih : p.inst) binary = binary || ih.dev.n_creases == 0;
-      if (binary) tiles = {0, 1, 2, 3};
+      if (binary) tiles = {0, 1, 2, 3, 4};
     }
     const std::string key = tune_key(p);
     int64_t best_seg = seg0;
@@ -872,7 +873,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
     double best_ms = 0.0;
     if (cache_lookup(cache_path, key, best_seg, best_lanes, best_tile) && best_lanes >= 1 &&
         best_lanes <= p.lanes_max && std::find(segs.begin(), segs.end(), best_seg) != segs.end() &&
-        best_tile >= 0 && best_tile <= 3) {
+        best_tile >= 0 && best_tile <= 4) {
       set_decomposition(p, best_seg, best_tile);
       p.lanes = best_lanes;
     } else {

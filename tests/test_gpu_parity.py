@@ -134,7 +134,7 @@ def test_split_fzp2mm_vs_fp64_and_oracle():
     assert abs(m["fwhm_x"] / mo["fwhm_x"] - 1) < 1e-3 and abs(m["de"] / mo["de"] - 1) < 1e-3
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("N,M", [(3000, 48), (2500, 128), (4096, 384)])
 def test_split_shapes_ragged(N, M, variant):
     """Row tiles with a ragged tail, column tiles wider than 2M, several K stages,
@@ -249,7 +249,7 @@ def test_fzp1m_sampled_stripes_split():
     _sampled_stripes("fzp1m", "split", [N // 2 - 64])
 
 
-@pytest.mark.parametrize("variant", [0, 1, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_fzp1m_sampled_stripes_split_variants(variant):
     N = workload("fzp1m")["N"]
     _sampled_stripes("fzp1m", "split", [N // 2 - 64, 777 * 128], variant=variant)
