@@ -209,8 +209,9 @@ __device__ __forceinline__ double2 to_c64(float2 v) { return make_double2((doubl
 // Column pass: one work-group per ROI column q (grid-stride).  Adds
 // F[p,q] Qy[p] sum_blocks(...) into roi[p][q]; each ROI element is owned by one
 // work-group, so the float64 sum over chunks is a fixed-order sequence.
-// T holds nseg partial row-pass results (K segments of the split path),
-// seg_stride complex elements apart; they are summed here in float64.
+// FP64 path: T[j][q] complex float64, row-major.  Split path: nseg float32
+// partial planes (K segments), seg_stride complex elements apart, each stored
+// column-major per real column; they are summed here in float64.
 template <int NQ, typename TT>
 __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t row_begin, int64_t row_end,
                                                              const TT *__restrict__ T, int nseg, int64_t seg_stride,
@@ -227,10 +228,20 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   for (int q = q0; q < M; q += gridDim.x) {
     double2 acc[NQ];
     bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, [&](int64_t j) -> double2 {
-      const TT *src = T + (j - row_begin) * (int64_t)M + q;
-      double2 g = to_c64(src[0]);
-      for (int sgi = 1; sgi < nseg; ++sgi) g = cadd(g, to_c64(src[sgi * seg_stride]));
-      return g;
+      if constexpr (sizeof(TT) == sizeof(float2)) {
+        // split path: float32 partial planes, column-major per real column
+        // (re = column 2q, im = column 2q + 1, row stride rs = chunk rows)
+        const int64_t rs = seg_stride / M;
+        const float *src = (const float *)T + (int64_t)(2 * q) * rs + (j - row_begin);
+        double2 g = make_double2((double)src[0], (double)src[rs]);
+        for (int sgi = 1; sgi < nseg; ++sgi) {
+          const float *p = src + (int64_t)sgi * 2 * seg_stride;
+          g = cadd(g, make_double2((double)p[0], (double)p[rs]));
+        }
+        return g;
+      } else {
+        return to_c64(T[(j - row_begin) * (int64_t)M + q]);
+      }
     });
     const double xq = d.x0 + ((double)q - 0.5 * (double)M) * d.dx_out;
 #pragma unroll

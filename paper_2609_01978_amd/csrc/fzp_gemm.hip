@@ -233,6 +233,35 @@ __device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t
   hi = (hi2 / 2 < N - 1 ? hi2 / 2 : N - 1) + 1;
 }
 
+// Epilogue of both row-pass GEMMs.  The partial sums are stored column-major,
+// Ts[c][r - row_begin] with column stride rs (the chunk's row count), so the
+// column pass reads each real column of T contiguously.  Register v of lane l
+// holds row 8(v/4) + 4(l/32) + (v%4) of its 32 x 32 block and column l%32: the
+// four registers 4a .. 4a+3 are four consecutive rows, one 16-byte store.
+__device__ __forceinline__ void store_partials(const f32x16 (&acc)[4][2], float *__restrict__ Ts, int64_t rs, int cbase,
+                                               int M2, int64_t rbase, int64_t row_begin, int64_t row_end) {
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int c = cbase + cb * 32;
+    if (c >= M2) continue;
+    float *col = Ts + (int64_t)c * rs - row_begin;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r = rbase + rb * 32 + 8 * a;
+        if (r + 3 < row_end) {
+          *(float4 *)(col + r) = make_float4(acc[rb][cb][4 * a], acc[rb][cb][4 * a + 1], acc[rb][cb][4 * a + 2],
+                                             acc[rb][cb][4 * a + 3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r + e < row_end) col[r + e] = acc[rb][cb][4 * a + e];
+        }
+      }
+  }
+}
+
 template <int WR, int RING, bool PF, bool IL>
 __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
                                                                 int n_rt, int n_ct, int seg_lo, int n_seg,
@@ -435,18 +464,8 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   // epilogue: register v of lane l holds row 8(v/4) + 4(l/32) + (v%4), column l%32
-  float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int c = c0 + wc * 64 + cb * 32 + l32;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = r0 + wr * 128 + rb * 32 + 8 * (v >> 2) + 4 * lhi + (v & 3);
-        if (r < row_end && c < M2) Ts[(r - row_begin) * (int64_t)M2 + c] = acc[rb][cb][v];
-      }
-    }
+  store_partials(acc, T + (int64_t)(seg - seg_lo) * seg_stride_f, seg_stride_f / M2, c0 + wc * 64 + l32, M2,
+                 r0 + wr * 128 + 4 * lhi, row_begin, row_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,18 +733,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, 
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
-  float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int c = c0 + wc * 64 + cb * 32 + l32;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = r0 + wr * 128 + rb * 32 + 8 * (v >> 2) + 4 * lhi + (v & 3);
-        if (r < row_end && c < M2) Ts[(r - row_begin) * (int64_t)M2 + c] = acc[rb][cb][v];
-      }
-    }
+  store_partials(acc, T + (int64_t)(seg - seg_lo) * seg_stride_f, seg_stride_f / M2, c0 + wc * 64 + l32, M2,
+                 r0 + wr * 128 + 4 * lhi, row_begin, row_end);
 }
 
 }  // namespace
