@@ -48,24 +48,38 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# sources of the dominant kernel (k_row_pass_split); its committed HBM counters
+# are reported only while these are unchanged
+GEMM_SOURCES = ["paper_2609_01978_amd/csrc/fzp_gemm.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
+
 # MI355X published peaks
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
-def committed_traffic(kernel_src: str, summary: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernel source changed since the counters were taken."""
+def kernel_sources_sha256(kernel_srcs) -> str:
+    """SHA-256 over the concatenated kernel source files (repository-relative)."""
     import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in kernel_srcs:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel_srcs, summary: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since the counters were taken."""
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         text = open(os.path.join(here, summary)).read()
-        src = open(os.path.join(here, kernel_src), "rb").read()
+        digest = kernel_sources_sha256(kernel_srcs)
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("|", "#")))
-    if vals.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+    if vals.get("kernel_source_sha256", "").strip() != digest:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -229,8 +243,8 @@ def main():
     row_ms_step = pr["row_ms"] / max(args.steps, 1)
     flops_step = 8.0 * M * disc
     achieved = flops_step / (row_ms_step * 1e-3) / 1e12
-    traffic = committed_traffic("paper_2609_01978_amd/csrc/fzp_gemm.hip",
-                                "profiles/hbm_traffic_k_row_pass_split_fzp1m.md") if args.workload == "fzp1m" else None
+    traffic = committed_traffic(GEMM_SOURCES, "profiles/hbm_traffic_k_row_pass_split_fzp1m.md") \
+        if args.workload == "fzp1m" else None
     roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
                     traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

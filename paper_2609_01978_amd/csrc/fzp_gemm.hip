@@ -19,22 +19,13 @@
 
 #include <cmath>
 
-#include "fzp_device.h"
-#include "fzp_internal.h"
+#include "fzp_split.h"
 
 namespace fzp {
 
 namespace {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
-typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 __device__ __forceinline__ double bf16_to_double(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
 
 __global__ __launch_bounds__(256) void k_build_split_table(InstDev d, uint16_t *At) {
@@ -145,7 +136,7 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
 // in the order chunk ^ swz(r), which keeps the MFMA operand reads (32
 // consecutive rows, one chunk) free of bank conflicts without padding.
 // ---------------------------------------------------------------------------
-constexpr int kThreads = 512;   // threads of the 512-row variant and of the complex kernel
+
 constexpr int kTC = 128;     // real columns per tile (64 complex ROI columns)
 constexpr int kKT = 32;      // K columns per pipeline stage
 constexpr int kRowB = 64;    // LDS bytes per slab row of a stage
@@ -188,16 +179,7 @@ template <int N> __device__ __forceinline__ void wait_barrier() {
 }
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
-__device__ __forceinline__ u32x4 lds_ld16(const char *p) { return *(const u32x4 *)p; }
 
-// Every wave issues exactly 3 copies per stage; waiting until at most 6 are
-// outstanding completes the copies issued two stages ago (those of the next
-// stage), then the work-group barrier makes them visible.  One asm statement,
-// so that the compiler does not put a wait for all outstanding copies in
-// front of the barrier.
-__device__ __forceinline__ void stage_barrier() {
-  asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 // 8 mask bits (one byte, column order) -> 8 packed BF16 values (1.0 / 0).
 // y = x | x << 15 puts bit 2p at bit 2p and bit 2p+1 at bit 2p+16; masking
@@ -213,54 +195,7 @@ __device__ __forceinline__ bf16x8 expand8(uint32_t x) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// Disc chord of the tile rows [r0, r1] (union = chord of the row nearest the axis),
-// in aperture columns [lo, hi).
-__device__ __forceinline__ void tile_chord(const InstDev &d, int64_t r0, int64_t r1, int64_t &lo, int64_t &hi) {
-  const int64_t N = d.N;
-  int64_t rc = (N - 1) / 2;
-  if (rc < r0) rc = r0;
-  if (rc > r1) rc = r1;
-  double cc = fabs((double)(2 * rc - N + 1));
-  if (rc + 1 <= r1) cc = fmin(cc, fabs((double)(2 * (rc + 1) - N + 1)));
-  const double rem = d.kmax - cc * cc;
-  lo = hi = 0;
-  if (rem < 0.0) return;
-  int64_t m = (int64_t)sqrt(rem);
-  while ((double)(m + 1) * (double)(m + 1) <= rem) ++m;
-  while (m > 0 && (double)m * (double)m > rem) --m;
-  const int64_t lo2 = N - 1 - m, hi2 = N - 1 + m;
-  lo = lo2 >= 0 ? (lo2 + 1) / 2 : 0;
-  hi = (hi2 / 2 < N - 1 ? hi2 / 2 : N - 1) + 1;
-}
 
-// Epilogue of both row-pass GEMMs.  The partial sums are stored column-major,
-// Ts[c][r - row_begin] with column stride rs (the chunk's row count), so the
-// column pass reads each real column of T contiguously.  Register v of lane l
-// holds row 8(v/4) + 4(l/32) + (v%4) of its 32 x 32 block and column l%32: the
-// four registers 4a .. 4a+3 are four consecutive rows, one 16-byte store.
-__device__ __forceinline__ void store_partials(const f32x16 (&acc)[4][2], float *__restrict__ Ts, int64_t rs, int cbase,
-                                               int M2, int64_t rbase, int64_t row_begin, int64_t row_end) {
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int c = cbase + cb * 32;
-    if (c >= M2) continue;
-    float *col = Ts + (int64_t)c * rs - row_begin;
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int64_t r = rbase + rb * 32 + 8 * a;
-        if (r + 3 < row_end) {
-          *(float4 *)(col + r) = make_float4(acc[rb][cb][4 * a], acc[rb][cb][4 * a + 1], acc[rb][cb][4 * a + 2],
-                                             acc[rb][cb][4 * a + 3]);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (r + e < row_end) col[r + e] = acc[rb][cb][4 * a + e];
-        }
-      }
-  }
-}
 
 template <int WR, int RING, bool PF, bool IL>
 __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_row_pass_split(InstDev d, int64_t row_begin, int64_t row_end,
@@ -468,275 +403,6 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
                  r0 + wr * 128 + 4 * lhi, row_begin, row_end);
 }
 
-// ---------------------------------------------------------------------------
-// Deformed stripes.  With a membrane phase screen the stripe
-// g = mask exp(2 pi i phi) is complex and the row pass is the full complex
-// product
-//   T_re = g_re.A_re - g_im.A_im,    T_im = g_re.A_im + g_im.A_re,
-// with both operands split into BF16 hi + lo and the three leading products
-//   g.A ~ g_hi.A_hi + g_hi.A_lo + g_lo.A_hi
-// (g_lo.A_lo is below 2^-32 relative and dropped).  Against the table's
-// interleaved columns [A_re | A_im] the imaginary stripe needs the columns
-// [-A_im | A_re]: the MFMA B operand of column n is swapped with that of its
-// neighbour n ^ 1 (a lane-pair DPP move, the two lanes hold the same k range)
-// and negated on even columns, so both products read the same LDS slab.
-//
-// The stripe is generated once per chunk (phase screen in FP32 turns from
-// FP64 ridge distances; zone mask from the exact integer rule) into
-//   G[v][kb][row][16],  v = re_hi, re_lo, im_hi, im_lo,
-// kb = 16-column block of the chunk's disc chord, rows padded to the 256-row
-// tile, so one pipeline stage of a row tile is a contiguous 8 KiB per plane.
-// ---------------------------------------------------------------------------
-constexpr int kCTR = 256;     // rows per tile
-constexpr int kCTC = 256;     // real columns per tile (128 complex ROI columns)
-constexpr int kCKT = 16;      // K columns per pipeline stage (one MFMA K-step)
-constexpr int kCRowB = 32;    // LDS bytes per slab row
-constexpr int kCGBytes = 4 * kCTR * kCRowB;   // 32768: four stripe planes
-constexpr int kCBBytes = 2 * kCTC * kCRowB;   // 16384: table hi and lo
-constexpr int kCStage = kCGBytes + kCBBytes;  // 49152
-constexpr int kCRing = 3, kCAhead = 2;
-constexpr int kCLdsBytes = kCRing * kCStage;  // 147456
-
-// 16-byte half of a 32-byte slab row in LDS: swapped on rows 8..15 of every
-// 16 so that 16 consecutive rows read at one half hit 64 distinct banks.
-__device__ __forceinline__ int chalf(int row, int half) { return half ^ ((row >> 3) & 1); }
-
-__global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
-                                                     int64_t rows_pad, int64_t kb0, int64_t nkb,
-                                                     uint16_t *__restrict__ G) {
-  const int64_t rl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (rl >= rows_pad) return;
-  const int64_t N = d.N;
-  const int64_t row = row_begin + rl;
-  const bool live = row < row_end;
-  const double cj = (double)(2 * row - N + 1);
-  const double bj = cj * cj;
-  const double y = 0.5 * cj * d.dx;
-  const double hdx = 0.5 * d.dx;
-  const int nc = d.n_creases;
-  const CreaseDev *cr = d.cr;
-  const int64_t plane = nkb * rows_pad * 16;
-  for (int64_t kb = blockIdx.y; kb < nkb; kb += gridDim.y) {
-    const int64_t i0 = 16 * (kb0 + kb);
-    const double c0 = (double)(2 * i0 - N + 1);
-    // zone mask of the 16 samples (exact integer rule)
-    uint32_t open = 0;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const double ci = c0 + 2.0 * e;
-      const double K = fma(ci, ci, bj);
-      const int zone = (int)(K * d.kappa);
-      const bool o = live && i0 + e < N && K <= d.kmax && (((zone & 1) ^ d.centre_open) != 0);
-      open |= (o ? 1u : 0u) << e;
-    }
-    // Crease phase in turns.  Along the row the ridge distance d grows by
-    // st = dx cos(theta) per sample, so the Gaussian g = exp(-a d^2) obeys
-    // g(i+1) = g(i) r(i) with r(i+1) = r(i) q, r(0) = exp(-a (2 d0 st + st^2)),
-    // q = exp(-2 a st^2): three exponentials per ridge per 16 samples, started
-    // from the float64 distance of the first sample.
-    float turns[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) turns[e] = 0.0f;
-    const double x0 = hdx * c0;
-    for (int k = 0; k < nc; ++k) {
-      const float dd = (float)fma(x0, cr[k].c, fma(y, cr[k].s, -cr[k].rho));
-      const float st = (float)(d.dx * cr[k].c);
-      const float a = (float)cr[k].inv2s2;
-      const float h = (float)cr[k].h_over_lambda;
-      float g = __expf(-a * dd * dd);
-      float r = __expf(-a * (2.0f * dd * st + st * st));
-      const float q = __expf(-2.0f * a * st * st);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        turns[e] = fmaf(h, g, turns[e]);
-        g *= r;
-        r *= q;
-      }
-    }
-    uint32_t w[4][8];
-#pragma unroll
-    for (int e = 0; e < 16; e += 2) {
-      uint32_t pr[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        float t = turns[e + u];
-        t -= rintf(t);
-        float sn, cs;
-        sincospif(2.0f * t, &sn, &cs);
-        const bool o = (open >> (e + u)) & 1u;
-        const float gr = o ? cs : 0.0f, gi = o ? sn : 0.0f;
-        const uint16_t rh = bf16_rne(gr), ih = bf16_rne(gi);
-        const uint16_t rlo = bf16_rne(gr - __uint_as_float((uint32_t)rh << 16));
-        const uint16_t ilo = bf16_rne(gi - __uint_as_float((uint32_t)ih << 16));
-        pr[0] |= (uint32_t)rh << (16 * u);
-        pr[1] |= (uint32_t)rlo << (16 * u);
-        pr[2] |= (uint32_t)ih << (16 * u);
-        pr[3] |= (uint32_t)ilo << (16 * u);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) w[v][e >> 1] = pr[v];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      u32x4 *dst = (u32x4 *)(G + v * plane + (kb * rows_pad + rl) * 16);
-      dst[0] = u32x4{w[v][0], w[v][1], w[v][2], w[v][3]};
-      dst[1] = u32x4{w[v][4], w[v][5], w[v][6], w[v][7]};
-    }
-  }
-}
-
-// Column n's B operand from lane l ^ 1 (column n ^ 1), negated on even columns.
-__device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
-  u32x4 u = __builtin_bit_cast(u32x4, b), r;
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    r[j] = (uint32_t)__builtin_amdgcn_mov_dpp((int)u[j], 0xb1, 0xf, 0xf, true) ^ nmask;  // quad_perm [1,0,3,2]
-  return __builtin_bit_cast(bf16x8, r);
-}
-
-// Row-pass GEMM for complex stripes.  Work-group tile: kCTR aperture rows x
-// kCTC real columns of T over one K segment (trimmed to the tiles' disc
-// chord).  8 waves in a 2 (rows) x 4 (columns) grid, each 128 x 64 = 4 x 2
-// MFMA 32x32 blocks (128 float32 accumulators per lane), 6 MFMAs per block
-// per K-step.  Stripe and table slabs move HBM -> LDS by direct copies into a
-// 3-deep ring, 2 stages ahead, one barrier per stage.
-__global__ __launch_bounds__(kThreads, 1) void k_row_pass_split_cplx(InstDev d, int64_t row_begin,
-                                                                     int64_t row_end, int n_rt, int n_ct,
-                                                                     int seg_lo, int n_seg,
-                                                                     const uint16_t *__restrict__ G,
-                                                                     int64_t rows_pad, int64_t kb0, int64_t nkb,
-                                                                     float *__restrict__ T, int64_t seg_stride_f) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int G_ = n_rt * n_ct * n_seg;
-  const int slot = blockIdx.x >> 3;
-  const int g = (slot >> 5) * 256 + (blockIdx.x & 7) * 32 + (slot & 31);
-  if (g >= G_) return;
-  const int rt = g % n_rt;
-  const int ct = (g / n_rt) % n_ct;
-  const int seg = seg_lo + g / (n_rt * n_ct);
-
-  const int M2 = 2 * d.M;
-  const int64_t r0 = row_begin + (int64_t)rt * kCTR;
-  int64_t rl = r0 + kCTR - 1;
-  if (rl > row_end - 1) rl = row_end - 1;
-  const int c0 = ct * kCTC;
-  const int64_t s_lo = (int64_t)seg * d.seg_len;
-  const int64_t s_hi = s_lo + d.seg_len < d.Npad ? s_lo + d.seg_len : d.Npad;
-  int64_t k_lo, k_hi;
-  tile_chord(d, r0, rl, k_lo, k_hi);
-  k_lo = k_lo / kCKT * kCKT;
-  k_hi = (k_hi + kCKT - 1) / kCKT * kCKT;
-  if (k_lo < s_lo) k_lo = s_lo;
-  if (k_hi > s_hi) k_hi = s_hi;
-  if (k_lo < 16 * kb0) k_lo = 16 * kb0;
-  if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
-
-  // ---- copy roles.  Stripe: wave w copies slab pieces x = 4w .. 4w+3 (plane
-  // x / 8, rows 32 (x % 8) ..); table: pieces y = 2w, 2w+1 (plane y / 8,
-  // columns 32 (y % 8) ..).  Lane L fills LDS row L / 2, half L & 1, which
-  // holds global half chalf(row, L & 1).  Table columns past 2M read column 0:
-  // they feed only accumulator columns that are never stored.
-  const int64_t plane = nkb * rows_pad * 16;
-  const uint16_t *gsrc[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int x = 4 * wave + j;
-    const int row = (x & 7) * 32 + (lane >> 1);
-    gsrc[j] = G + (x >> 3) * plane + ((int64_t)rt * kCTR + row) * 16 + 8 * chalf(row, lane & 1);
-  }
-  const uint16_t *bsrc[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int y = 2 * wave + j;
-    const int col = (y & 7) * 32 + (lane >> 1);
-    const int gc = c0 + col < M2 ? c0 + col : 0;
-    bsrc[j] = d.A + (int64_t)(y >> 3) * M2 * d.Npad + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
-  }
-
-  // ---- compute role: wave (wr, wc) covers rows wr*128 .., columns wc*64 ..
-  const int wr = wave >> 2, wc = wave & 3;
-  const int l32 = lane & 31, lhi = lane >> 5;
-  const int hofs = chalf(l32, lhi) * 16;
-  const int aoff = (wr * 128 + l32) * kCRowB + hofs;
-  const int boff = kCGBytes + (wc * 64 + l32) * kCRowB + hofs;
-  const uint32_t nmask = (lane & 1) ? 0u : 0x80008000u;
-
-  f32x16 acc[4][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
-
-  if (k_lo < k_hi) {
-    const int64_t kb = k_lo;
-    const int nst = (int)((k_hi - k_lo) / kCKT);
-    const int64_t klast = k_hi - kCKT;  // copies past the end repeat the last stage
-    auto copy_stage = [&](int s) {
-      const int64_t k = kb + (int64_t)s * kCKT < klast ? kb + (int64_t)s * kCKT : klast;
-      char *dst = lds + (s % kCRing) * kCStage;
-      const int64_t gofs = (k / 16 - kb0) * rows_pad * 16;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        __builtin_amdgcn_global_load_lds((const void *)(gsrc[j] + gofs),
-                                         (__attribute__((address_space(3))) void *)(dst + (4 * wave + j) * 1024),
-                                         16, 0, 0);
-      const int64_t bofs = (k >> 5) * M2 * 32 + (k & 31);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        __builtin_amdgcn_global_load_lds((const void *)(bsrc[j] + bofs),
-                                         (__attribute__((address_space(3))) void *)(dst + kCGBytes +
-                                                                                    (2 * wave + j) * 1024),
-                                         16, 0, 0);
-    };
-    for (int s = 0; s < kCAhead; ++s) copy_stage(s);
-    asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
-    for (int s = 0; s < nst; ++s) {
-      copy_stage(s + kCAhead);
-      const char *sb = lds + (s % kCRing) * kCStage;
-      bf16x8 bh[2], bl[2], bhs[2], bls[2];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB));
-        bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB + kCTC * kCRowB));
-        bhs[cb] = swap_neg(bh[cb], nmask);
-        bls[cb] = swap_neg(bl[cb], nmask);
-      }
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const char *pa = sb + aoff + rb * 32 * kCRowB;
-        const bf16x8 rh = __builtin_bit_cast(bf16x8, lds_ld16(pa));
-        const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
-        const bf16x8 ih = __builtin_bit_cast(bf16x8, lds_ld16(pa + 2 * kCTR * kCRowB));
-        const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bh[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bhs[cb], acc[rb][cb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bls[cb], acc[rb][cb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
-        }
-      }
-      stage_barrier();
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  }
-  store_partials(acc, T + (int64_t)(seg - seg_lo) * seg_stride_f, seg_stride_f / M2, c0 + wc * 64 + l32, M2,
-                 r0 + wr * 128 + 4 * lhi, row_begin, row_end);
-}
-
 }  // namespace
 
 hipError_t init_split_attributes() {
@@ -756,9 +422,7 @@ hipError_t init_split_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<2, 4>::lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kCLdsBytes);
+  if (e == hipSuccess) e = init_cplx_attributes();
   if (e == hipSuccess) done = true;
   return e;
 }
@@ -864,54 +528,6 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   if (d.bin_ring == 8)
     return launch_bin<4, 8, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
   return launch_bin<4, 4, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
-}
-
-}  // namespace fzp
-
-namespace fzp {
-
-size_t split_stripe_bytes(const InstDev &d, int64_t chunk_rows) {
-  const int64_t rows_pad = (chunk_rows + kCTR - 1) / kCTR * kCTR;
-  return (size_t)rows_pad * (size_t)d.Npad * 4 * sizeof(uint16_t);
-}
-
-void split_stripe_extent(const InstDev &d, int64_t row_begin, int64_t row_end, int64_t &rows_pad, int64_t &kb0,
-                         int64_t &nkb) {
-  int64_t lo, hi;
-  split_chunk_chord(d, row_begin, row_end, lo, hi);
-  rows_pad = (row_end - row_begin + kCTR - 1) / kCTR * kCTR;
-  kb0 = lo / 16;
-  nkb = hi > lo ? (hi + 15) / 16 - kb0 : 0;
-}
-
-hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, uint16_t *G, hipStream_t st) {
-  int64_t rows_pad, kb0, nkb;
-  split_stripe_extent(d, row_begin, row_end, rows_pad, kb0, nkb);
-  if (nkb <= 0 || rows_pad <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)(nkb < 65535 ? nkb : 65535));
-  hipLaunchKernelGGL(k_stripe_cplx, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T,
-                                      int64_t seg_stride, const uint16_t *G, hipStream_t st) {
-  const int64_t rows = row_end - row_begin;
-  if (rows <= 0) return hipSuccess;
-  int64_t rows_pad, kb0, nkb;
-  split_stripe_extent(d, row_begin, row_end, rows_pad, kb0, nkb);
-  int seg_lo, seg_hi;
-  split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
-  if (seg_hi <= seg_lo || nkb <= 0) return hipSuccess;
-  const int n_rt = (int)((rows + kCTR - 1) / kCTR);
-  const int n_ct = (2 * d.M + kCTC - 1) / kCTC;
-  const int n_seg = seg_hi - seg_lo;
-  const int64_t Gn = (int64_t)n_rt * n_ct * n_seg;
-  const int64_t grid = (Gn + 255) / 256 * 256;
-  hipError_t e = init_split_attributes();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_pass_split_cplx, dim3((unsigned)grid), dim3(kThreads), kCLdsBytes, st, d, row_begin,
-                     row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride);
-  return hipGetLastError();
 }
 
 }  // namespace fzp

@@ -115,6 +115,7 @@ void set_last_error(const std::string &msg);
 hipError_t launch_build_tables(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
 hipError_t launch_build_split_table(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);
 hipError_t init_split_attributes();  // kernel attributes of the split GEMMs (outside graph capture)
+hipError_t init_cplx_attributes();   // the complex-stripe GEMM's part of it (fzp_cplx.hip)
 hipError_t launch_zero(double *buf, int64_t n_doubles, hipStream_t st);
 hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row_end, double2 *T,
                                 hipStream_t st);
