@@ -274,3 +274,46 @@ def test_fzp20mm_creased_stripes_split():
         e = rel_l2(U, ref)
         announce(f"  complex rel-L2 {e:.3e}")
         assert e <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Whole apertures at the large workloads: both paths, metrics against the
+# oracle's extractor, the radial (Hankel) integral and the Airy closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["fzp20mm", "fzp1m"])
+def test_full_aperture_metrics(name):
+    w = workload(name)
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    res = {}
+    for path in ("split", "fp64"):
+        announce(f"{name} full aperture, {path}")
+        plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"])
+        ws, roi = plan.alloc()
+        plan.propagate(ws, roi)
+        m = plan.metrics(ws, roi)[0]
+        U = plan.roi_view(roi, 0).cpu().numpy()
+        res[path] = (U, m)
+        del ws, roi
+        torch.cuda.empty_cache()
+    a, i = oracle_case(ap, inst)
+    I_split, I_fp64 = O.intensity(res["split"][0]), O.intensity(res["fp64"][0])
+    e = rel_l2(I_split, I_fp64)
+    announce(f"  split vs fp64 intensity rel-L2 {e:.3e}")
+    assert e <= 1e-4
+    h = O.hankel_metrics(a)
+    lz = w["lambda0"] * w["f0"]
+    airy_fwhm = O.AIRY_FWHM * lz / w["D"]
+    airy_de = O.AIRY_LOBE_FRACTION / np.pi ** 2
+    for path, (U, m) in res.items():
+        # the GPU extractor against the oracle's on the same ROI
+        mo = O.metrics(U, a, i)
+        for key in ("fwhm_x", "fwhm_y", "de", "strehl", "mtf_half_cut"):
+            assert abs(m[key] / mo[key] - 1) < 1e-8, (path, key, m[key], mo[key])
+        # FWHM and DE within 0.1 % of the continuous aperture and of the Airy forms
+        announce(f"  {path}: FWHM/Hankel-1 {m['fwhm_x'] / h['fwhm'] - 1:.2e}, DE/Hankel-1 {m['de'] / h['de'] - 1:.2e}, "
+                 f"FWHM/Airy-1 {m['fwhm_x'] / airy_fwhm - 1:.2e}, DE/Airy-1 {m['de'] / airy_de - 1:.2e}")
+        for key in ("fwhm_x", "fwhm_y"):
+            assert abs(m[key] / h["fwhm"] - 1) < 1e-3 and abs(m[key] / airy_fwhm - 1) < 1e-3
+        assert abs(m["de"] / h["de"] - 1) < 1e-3 and abs(m["de"] / airy_de - 1) < 1e-3
