@@ -114,6 +114,15 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
+// A loader either returns one sample, load(i), or, when it declares kBlock,
+// fills a whole block at once: load.block(i0, cnt, v) sets v[r] = g[i0 + n]
+// for n = threadIdx.x + 256 r < cnt and 0 otherwise (all of a block's loads can
+// then be in flight together).
+template <typename L, typename = void>
+struct IsBlockLoader : std::false_type {};
+template <typename L>
+struct IsBlockLoader<L, std::void_t<decltype(L::kBlock)>> : std::true_type {};
+
 // Blocked Bluestein over one line, shared by the row and column passes.
 // load(i) returns g[i] (only called for i in [i_start, i_end)).
 // The input chirp of block sample n = t + 256 r,
@@ -141,15 +150,25 @@ __device__ __forceinline__ void bluestein_line(const InstDev &d, const double2 *
     double2 ph = cexp_turns(frac_turns(lin * tt) + g0);
     double2 dl = cexp_turns(frac_turns(lin * 256.0) + g1);
     double2 v[16];
+    if constexpr (IsBlockLoader<Load>::value) {
+      load.block(i0, i_end - i0 < (int64_t)B ? i_end - i0 : (int64_t)B, v);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int n = t + 256 * r;
-      const int64_t i = i0 + n;
-      double2 g = make_double2(0.0, 0.0);
-      if (n < B && i < i_end) g = load(i);
-      v[r] = cmul(g, ph);
-      ph = cmul(ph, dl);
-      dl = cmul(dl, dd);
+      for (int r = 0; r < 16; ++r) {
+        v[r] = cmul(v[r], ph);
+        ph = cmul(ph, dl);
+        dl = cmul(dl, dd);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = t + 256 * r;
+        const int64_t i = i0 + n;
+        double2 g = make_double2(0.0, 0.0);
+        if (n < B && i < i_end) g = load(i);
+        v[r] = cmul(g, ph);
+        ph = cmul(ph, dl);
+        dl = cmul(dl, dd);
+      }
     }
     fft4096<-1>(v, s_lds, tw);
     const double2 *__restrict__ Hb = H + opaque_zero();
@@ -206,6 +225,43 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_row_pass_fp64(InstDev d, int
 __device__ __forceinline__ double2 to_c64(double2 v) { return v; }
 __device__ __forceinline__ double2 to_c64(float2 v) { return make_double2((double)v.x, (double)v.y); }
 
+// Split-path column input: the float32 partial planes of one ROI column
+// (real column 2q, imaginary column 2q + 1 = rs floats further), nseg planes
+// `plane` floats apart, summed in float64 in plane order.  Each plane's 32
+// loads of a block are issued before any is used.
+struct SplitColumn {
+  static constexpr bool kBlock = true;
+  const float *re;  // plane 0, real column, row row_begin
+  int64_t rs;
+  int64_t plane;
+  int nseg;
+  int64_t row_begin;
+  __device__ __forceinline__ void block(int64_t i0, int64_t cnt, double2 v[16]) const {
+    const int t = threadIdx.x;
+    const float *src = re + (i0 - row_begin);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = make_double2(0.0, 0.0);
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+      const float *p = src + (int64_t)sgi * plane;
+      float a[16], b[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = t + 256 * r;
+        const int k = n < cnt ? n : 0;  // lanes past the block re-read row i0
+        a[r] = p[k];
+        b[r] = p[rs + k];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (t + 256 * r < cnt) {
+          v[r].x += (double)a[r];
+          v[r].y += (double)b[r];
+        }
+      }
+    }
+  }
+};
+
 // Column pass: one work-group per ROI column q (grid-stride).  Adds
 // F[p,q] Qy[p] sum_blocks(...) into roi[p][q]; each ROI element is owned by one
 // work-group, so the float64 sum over chunks is a fixed-order sequence.
@@ -227,22 +283,16 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   if (gridDim.x == (unsigned)M && (M & 7) == 0) q0 = (q0 & 7) * (M >> 3) + (q0 >> 3);
   for (int q = q0; q < M; q += gridDim.x) {
     double2 acc[NQ];
-    bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, [&](int64_t j) -> double2 {
-      if constexpr (sizeof(TT) == sizeof(float2)) {
-        // split path: float32 partial planes, column-major per real column
-        // (re = column 2q, im = column 2q + 1, row stride rs = chunk rows)
-        const int64_t rs = seg_stride / M;
-        const float *src = (const float *)T + (int64_t)(2 * q) * rs + (j - row_begin);
-        double2 g = make_double2((double)src[0], (double)src[rs]);
-        for (int sgi = 1; sgi < nseg; ++sgi) {
-          const float *p = src + (int64_t)sgi * 2 * seg_stride;
-          g = cadd(g, make_double2((double)p[0], (double)p[rs]));
-        }
-        return g;
-      } else {
-        return to_c64(T[(j - row_begin) * (int64_t)M + q]);
-      }
-    });
+    if constexpr (sizeof(TT) == sizeof(float2)) {
+      // split path: float32 partial planes, column-major per real column
+      // (re = column 2q, im = column 2q + 1, row stride rs = chunk rows)
+      const int64_t rs = seg_stride / M;
+      const SplitColumn col{(const float *)T + (int64_t)(2 * q) * rs, rs, 2 * seg_stride, nseg, row_begin};
+      bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, col);
+    } else {
+      bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc,
+                         [&](int64_t j) -> double2 { return to_c64(T[(j - row_begin) * (int64_t)M + q]); });
+    }
     const double xq = d.x0 + ((double)q - 0.5 * (double)M) * d.dx_out;
 #pragma unroll
     for (int r = 0; r < NQ; ++r) {
