@@ -55,7 +55,7 @@ constexpr int kCLdsBytes = kCRing * kCStage;  // 147456
 // 16 so that 16 consecutive rows read at one half hit 64 distinct banks.
 __device__ __forceinline__ int chalf(int row, int half) { return half ^ ((row >> 3) & 1); }
 
-__global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
+__global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
                                                      int64_t rows_pad, int64_t kb0, int64_t nkb,
                                                      uint16_t *__restrict__ G) {
   const int64_t rl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -70,8 +70,19 @@ __global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begi
   const int nc = d.n_creases;
   const CreaseDev *cr = d.cr;
   const int64_t plane = nkb * rows_pad * 16;
+  // The GEMM reads a row tile's slab only inside that tile's disc chord
+  // (rounded out to whole 16-column blocks): blocks outside it are not written.
+  int64_t t_lo, t_hi;
+  {
+    const int64_t r0 = row_begin + (int64_t)blockIdx.x * kCTR;
+    const int64_t r1 = r0 + kCTR - 1 < row_end - 1 ? r0 + kCTR - 1 : row_end - 1;
+    tile_chord(d, r0, r1, t_lo, t_hi);
+    t_lo = t_lo / 16 * 16;
+    t_hi = (t_hi + 15) / 16 * 16;
+  }
   for (int64_t kb = blockIdx.y; kb < nkb; kb += gridDim.y) {
     const int64_t i0 = 16 * (kb0 + kb);
+    if (i0 < t_lo || i0 >= t_hi) continue;
     const double c0 = (double)(2 * i0 - N + 1);
     // zone mask of the 16 samples (exact integer rule)
     uint32_t open = 0;
@@ -87,7 +98,10 @@ __global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begi
     // st = dx cos(theta) per sample, so the Gaussian g = exp(-a d^2) obeys
     // g(i+1) = g(i) r(i) with r(i+1) = r(i) q, r(0) = exp(-a (2 d0 st + st^2)),
     // q = exp(-2 a st^2): three exponentials per ridge per 16 samples, started
-    // from the float64 distance of the first sample.
+    // from the float64 distance of the first sample.  A ridge whose term stays
+    // below 2^-30 turns over all 16 samples (|h| exp(-a d^2) < 2^-30 at the
+    // nearest of them) is skipped; neighbouring rows of a wave see nearly the
+    // same distances, so the skip is close to wave-uniform.
     float turns[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) turns[e] = 0.0f;
@@ -97,6 +111,9 @@ __global__ __launch_bounds__(256) void k_stripe_cplx(InstDev d, int64_t row_begi
       const float st = (float)(d.dx * cr[k].c);
       const float a = (float)cr[k].inv2s2;
       const float h = (float)cr[k].h_over_lambda;
+      const float d15 = fmaf(15.0f, st, dd);
+      const float dmin = (dd > 0.0f) == (d15 > 0.0f) ? fminf(fabsf(dd), fabsf(d15)) : 0.0f;
+      if (a * dmin * dmin > __logf(fabsf(h)) + 20.7944154f) continue;  // ln 2^30
       float g = __expf(-a * dd * dd);
       float r = __expf(-a * (2.0f * dd * st + st * st));
       const float q = __expf(-2.0f * a * st * st);
@@ -316,8 +333,16 @@ hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_e
   int64_t rows_pad, kb0, nkb;
   split_stripe_extent(d, row_begin, row_end, rows_pad, kb0, nkb);
   if (nkb <= 0 || rows_pad <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)(nkb < 65535 ? nkb : 65535));
-  hipLaunchKernelGGL(k_stripe_cplx, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
+  // x: one work-group row per 256-row GEMM tile (the kernel takes that tile's
+  // chord); y: about 4096 work-groups in all, each striding over the 16-column
+  // blocks (measured a little faster than one work-group per block)
+  const int64_t gx = (rows_pad + kCTR - 1) / kCTR;
+  int64_t gy = 4096 / gx;
+  if (gy < 1) gy = 1;
+  if (gy > nkb) gy = nkb;
+  if (gy > 65535) gy = 65535;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  hipLaunchKernelGGL(k_stripe_cplx, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
   return hipGetLastError();
 }
 
