@@ -317,3 +317,105 @@ def test_full_aperture_metrics(name):
         for key in ("fwhm_x", "fwhm_y"):
             assert abs(m[key] / h["fwhm"] - 1) < 1e-3 and abs(m[key] / airy_fwhm - 1) < 1e-3
         assert abs(m["de"] / h["de"] - 1) < 1e-3 and abs(m["de"] / airy_de - 1) < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Limits and degenerate cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("path,M", [("fp64", 2), ("fp64", 2048), ("split", 16), ("split", 2048)])
+def test_roi_size_limits(path, M):
+    """The smallest and largest ROI the plan accepts (M in 2 .. 2048; the split
+    path takes multiples of 16) against the oracle."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
+    inst = dict(lam=LAM0, M=M)
+    announce(f"{path} ROI size limit M={M}")
+    _, _, _, (U,) = run_gpu(ap, [inst], path=path)
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    if path == "fp64":
+        assert rel_l2(U, ref) < 1e-9
+    else:
+        e = rel_l2(O.intensity(U), O.intensity(ref))
+        announce(f"  intensity rel-L2 {e:.3e}")
+        assert e <= 1e-4
+
+
+@pytest.mark.parametrize("path", ["fp64", "split"])
+def test_aperture_smaller_than_one_tile(path):
+    """N = 100: fewer rows than one GEMM row tile, K shorter than one stage
+    block of the table, one Bluestein block per line."""
+    ap = dict(D=1e-3, f0=10e-3, lambda0=LAM0, N=100)
+    inst = dict(lam=LAM0, M=32)
+    announce(f"{path} N=100 M=32")
+    _, _, _, (U,) = run_gpu(ap, [inst], path=path, allow_undersampled=True)
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=64)
+    if path == "fp64":
+        assert rel_l2(U, ref) < 1e-9
+    else:
+        assert rel_l2(O.intensity(U), O.intensity(ref)) <= 1e-4
+
+
+@pytest.mark.parametrize("path", ["fp64", "split"])
+def test_empty_and_outside_row_ranges(path):
+    """An empty row range writes a zero ROI, or leaves it as it was when
+    accumulating; rows wholly outside the disc add exactly nothing."""
+    ap = dict(D=1e-3, f0=4e-3, lambda0=LAM0, N=1001, pitch=1e-3 / 997)
+    inst = dict(lam=LAM0, M=64, z=4.05e-3)
+    announce(f"{path} empty and outside-disc row ranges")
+    plan = P.Plan(ap, [inst], path=path, allow_undersampled=True)
+    ws, roi = plan.alloc()
+    roi.fill_(1.0)
+    plan.propagate_range(ws, roi, 0, 0, accumulate=False)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(roi)) == 0
+    # disc radius 997/2 samples about the centre of a 1001-sample grid: rows 0, 1 miss it
+    roi.fill_(1.0)
+    plan.propagate_range(ws, roi, 0, 2, accumulate=False)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(roi)) == 0
+    plan.propagate(ws, roi)
+    full = roi.clone()
+    plan.propagate_range(ws, roi, 500, 500, accumulate=True)
+    plan.propagate_range(ws, roi, 1001, 1001, accumulate=True)
+    plan.propagate_range(ws, roi, 999, 1001, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(roi, full)
+
+
+def test_zero_height_creases_match_binary():
+    """Creases of zero height take the complex-stripe kernels but must give
+    the undeformed plate: against the binary-stripe kernels of the same plan
+    shape."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=3000)
+    cr = crease_draws(11, 2e-3, LAM0, 8)
+    cr[:, 3] = 0.0
+    announce("split zero-height creases vs binary stripes")
+    _, _, _, (Uc,) = run_gpu(ap, [dict(lam=LAM0, M=128, creases=cr)], path="split", allow_undersampled=True)
+    _, _, _, (Ub,) = run_gpu(ap, [dict(lam=LAM0, M=128)], path="split", allow_undersampled=True)
+    e = rel_l2(O.intensity(Uc), O.intensity(Ub))
+    announce(f"  intensity rel-L2 {e:.3e}")
+    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("path", ["fp64", "split"])
+def test_largest_aperture_sampled_stripe(path):
+    """N = 2^21 (the largest grid the plan accepts): a 2 m f/5 plate at
+    0.95 um pitch, a stripe of 64 rows through the centre against the
+    oracle's restricted row sum."""
+    N = 1 << 21
+    ap = dict(D=2.0, f0=10.0, lambda0=LAM0, N=N)
+    inst = dict(lam=LAM0, M=512)
+    plan = P.Plan(ap, [inst], path=path, stripe_rows=64)
+    ws, roi = plan.alloc()
+    a, i = oracle_case(ap, inst)
+    j0 = N // 2 - 32
+    announce(f"N=2^21 {path} stripe rows {j0}..{j0 + 64}")
+    plan.propagate_range(ws, roi, j0, j0 + 64, accumulate=False)
+    torch.cuda.synchronize()
+    U = plan.roi_view(roi, 0).cpu().numpy()
+    ref = O.propagate(a, i, method="bluestein", rows=(j0, j0 + 64), stripe=16)
+    e = rel_l2(U, ref)
+    announce(f"  complex rel-L2 {e:.3e}")
+    assert e <= (1e-6 if path == "fp64" else 1e-4)
