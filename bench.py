@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
     ap.add_argument("--surrogate", action="store_true",
-                    help="also train and judge the learned surrogate (20k + 1k CZT solves)")
+                    help="also train and evaluate the learned surrogate (20k + 1k CZT solves)")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")

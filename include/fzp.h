@@ -229,7 +229,7 @@ void fzp_destroy(fzp_plan_t p);
  * deformations (introduction) and gives no learned model; the library adds a
  * multilayer perceptron from crease parameters and the wavelength to the ROI
  * log-intensity, trained on the propagation's own outputs, with the CZT as
- * judge and fallback:
+ * arbiter and fallback:
  *   z1 = W1 x + b1, h1 = silu(z1); z2 = W2 h1 + b2, h2 = silu(z2); y = W3 h2 + b3,
  *   silu(z) = z / (1 + e^{-z}),  loss = sum (y - t)^2 / (B n_out),
  * Adam updates (Kingma & Ba 2015, Algorithm 1; beta1 0.9, beta2 0.999,

@@ -2,7 +2,7 @@
 // wavelength to the log-intensity of the focal-plane ROI, trained on the
 // propagation's own outputs.  The paper motivates full 2-D simulation by
 // membrane deformations (introduction) but gives no learned model; this is
-// the network the library provides for that use, with the CZT as its judge.
+// the network the library provides for that use, with the CZT as its arbiter.
 //
 //   z1 = W1 x + b1, h1 = silu(z1);  z2 = W2 h1 + b2, h2 = silu(z2);
 //   y = W3 h2 + b3;  loss = sum (y - t)^2 / (B n_out)

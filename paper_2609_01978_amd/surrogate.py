@@ -6,7 +6,7 @@ the log-intensity ``ln(I / I0 + FLOOR)`` of the M x M focal-plane ROI, with
 ``I0 = (R^2 / (lambda0 f0))^2`` the peak scale of the undeformed plate (its
 on-axis intensity is close to the square of twice the number of open zones).
 It is trained on the split-BF16 CZT propagation of the same plate; the CZT is
-also its judge and its fallback: a 2-member ensemble is trained from two
+also its arbiter and its fallback: a 2-member ensemble is trained from two
 seeds, and a prediction is accepted only when the input lies inside the
 training box and the two members' FWHMs agree within a threshold calibrated
 on held-out validation solves so that accepted validation cases keep the FWHM
