@@ -55,16 +55,6 @@ __device__ __forceinline__ void row_chord(int64_t N, double kmax, double bj, int
   i_end = b + 1 > a ? b + 1 : a;
 }
 
-// Crease phase screen at (x, y): exp(2 pi i sum_k (H_k/lambda) exp(-d_k^2/(2 sigma_k^2))).
-__device__ __forceinline__ double2 crease_phasor(const CreaseDev *cr, int n, double x, double y) {
-  double turns = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double d = x * cr[k].c + y * cr[k].s - cr[k].rho;
-    turns += cr[k].h_over_lambda * exp(-d * d * cr[k].inv2s2);
-  }
-  return cexp_turns(turns);
-}
-
 __global__ void k_zero(double *buf, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     buf[i] = 0.0;
@@ -188,6 +178,58 @@ __device__ __forceinline__ void bluestein_line(const InstDev &d, const double2 *
   }
 }
 
+// Row-pass input of a deformed plate for a whole block: the zone mask times
+// the crease phase screen exp(2 pi i sum_k (H_k/lambda) exp(-d_k^2/(2 sigma_k^2))),
+// d_k = x cos(theta_k) + y sin(theta_k) - rho_k, along one aperture row.  The
+// thread's samples n = t + 256 r lie 256 samples apart, so along r each
+// ridge's distance grows by D = 256 dx cos(theta) and its Gaussian
+// g = exp(-a d^2) follows g(r+1) = g(r) R(r), R(r+1) = R(r) Q with
+// R(0) = exp(-a (2 d0 D + D^2)), Q = exp(-2 a D^2): three exponentials per
+// ridge per block instead of sixteen, in float64.  A ridge whose term stays
+// below 2^-52 turns at the nearest of the thread's samples is skipped.
+struct CreasedRow {
+  static constexpr bool kBlock = true;
+  const InstDev *d;
+  double bj, y;
+  __device__ __forceinline__ void block(int64_t i0, int64_t cnt, double2 v[16]) const {
+    const int t = threadIdx.x;
+    const int64_t N = d->N;
+    const double c0 = (double)(2 * (i0 + t) - N + 1);
+    const double x0 = 0.5 * c0 * d->dx;
+    bool open[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double ci = c0 + 512.0 * r;
+      const double K = ci * ci + bj;  // exact integer
+      const int zone = (int)(K * d->kappa);
+      open[r] = t + 256 * r < cnt && ((zone & 1) ^ d->centre_open) != 0;
+    }
+    double turns[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) turns[r] = 0.0;
+    for (int k = 0; k < d->n_creases; ++k) {
+      const CreaseDev &cr = d->cr[k];
+      const double a = cr.inv2s2, h = cr.h_over_lambda;
+      const double d0 = fma(x0, cr.c, fma(y, cr.s, -cr.rho));
+      const double D = 256.0 * d->dx * cr.c;
+      const double d15 = fma(15.0, D, d0);
+      const double dmin = (d0 > 0.0) == (d15 > 0.0) ? fmin(fabs(d0), fabs(d15)) : 0.0;
+      if (a * dmin * dmin > log(fabs(h)) + 36.0436533891) continue;  // ln 2^52
+      double g = exp(-a * d0 * d0);
+      double R = exp(-a * (2.0 * d0 * D + D * D));
+      const double Q = exp(-2.0 * a * D * D);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        turns[r] = fma(h, g, turns[r]);
+        g *= R;
+        R *= Q;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = open[r] ? cexp_turns(turns[r]) : make_double2(0.0, 0.0);
+  }
+};
+
 // Row pass: one work-group per aperture row (grid-stride), T[row - row_begin][q].
 template <int NQ, bool DEFORM>
 __global__ __launch_bounds__(kFftThreads, 2) void k_row_pass_fp64(InstDev d, int64_t row_begin, int64_t row_end,
@@ -204,15 +246,17 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_row_pass_fp64(InstDev d, int
     row_chord(N, d.kmax, bj, i_start, i_end);
     const double y = 0.5 * cj * d.dx;
     double2 acc[NQ];
-    bluestein_line<NQ>(d, d.Hx, d.sx, i_start, i_end, s_lds, tw, acc, [&](int64_t i) -> double2 {
-      const double ci = (double)(2 * i - N + 1);
-      const double K = ci * ci + bj;  // exact integer
-      const int zone = (int)(K * d.kappa);
-      const bool open = ((zone & 1) ^ d.centre_open) != 0;
-      double2 g = make_double2(open ? 1.0 : 0.0, 0.0);
-      if (DEFORM && open) g = crease_phasor(d.cr, d.n_creases, 0.5 * ci * d.dx, y);
-      return g;
-    });
+    if constexpr (DEFORM) {
+      bluestein_line<NQ>(d, d.Hx, d.sx, i_start, i_end, s_lds, tw, acc, CreasedRow{&d, bj, y});
+    } else {
+      bluestein_line<NQ>(d, d.Hx, d.sx, i_start, i_end, s_lds, tw, acc, [&](int64_t i) -> double2 {
+        const double ci = (double)(2 * i - N + 1);
+        const double K = ci * ci + bj;  // exact integer
+        const int zone = (int)(K * d.kappa);
+        const bool open = ((zone & 1) ^ d.centre_open) != 0;
+        return make_double2(open ? 1.0 : 0.0, 0.0);
+      });
+    }
     double2 *Trow = T + (row - row_begin) * (int64_t)M;
 #pragma unroll
     for (int r = 0; r < NQ; ++r) {
