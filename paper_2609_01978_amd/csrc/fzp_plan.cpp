@@ -263,10 +263,17 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       p.chunk_rows = c < N ? c : N;
     }
     if (split && cplx && o.chunk_rows <= 0) {
-      // the complex stripe planes (8 bytes per sample of a chunk) stay near 2 GiB
+      // the complex stripe planes (8 bytes per sample of a chunk) stay near
+      // 2 GiB, or grow up to 8 GiB while the GEMM grid of the smallest ROI
+      // (256-row x 256-column tiles times K segments) has fewer than 512 tiles
       const int64_t npad = (N + 63) / 64 * 64;
-      int64_t c = (int64_t)(((size_t)2 << 30) / ((size_t)npad * 8)) / 256 * 256;
+      const size_t per_row = (size_t)npad * 8;
+      int64_t c = (int64_t)(((size_t)2 << 30) / per_row) / 256 * 256;
       if (c < 256) c = 256;
+      int Mmin = p.Mmax;
+      for (const auto &ih : p.inst) Mmin = ih.dev.M < Mmin ? ih.dev.M : Mmin;
+      const int64_t n_ct = (2 * Mmin + 255) / 256;
+      while ((c / 256) * n_ct * nseg < 512 && c < N && (size_t)(2 * c) * per_row <= ((size_t)8 << 30)) c *= 2;
       if (c < p.chunk_rows) p.chunk_rows = c;
     }
     if (split) p.chunk_rows = (p.chunk_rows + p.S - 1) / p.S * p.S;

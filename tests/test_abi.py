@@ -115,14 +115,14 @@ def test_last_error_is_thread_local_message():
 
 def test_split_creased_plan_layout():
     """Deformed stripes on the split path: the plan adds the complex stripe planes
-    (8 bytes per sample of a chunk, chunks of whole 256-row tiles near 1 GiB)."""
+    (8 bytes per sample of a chunk, chunks of whole 256-row tiles up to 8 GiB)."""
     from fzp_inputs import crease_draws
     ap, w = ap_of("fzp20mm")
     flat = P.Plan(ap, [dict(lam=w["lambda0"], M=512)], path="split")
     cr = crease_draws(0, w["D"], w["lambda0"], 8)
     bent = P.Plan(ap, [dict(lam=w["lambda0"], M=512, creases=cr)], path="split")
     c = bent.info()["chunk_rows"]
-    assert c % 256 == 0 and c * w["N"] * 8 <= 2 ** 31
+    assert c % 256 == 0 and c * w["N"] * 8 <= 2 ** 33
     table = 2 * (2 * 512) * w["N"] * 2               # hi/lo planes of the N x 2M BF16 operand table
     assert bent.workspace_size >= table + c * w["N"] * 8
     assert flat.workspace_size < table + c * w["N"] * 8
