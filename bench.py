@@ -161,8 +161,8 @@ def run_batch(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
-              "(the stripe-range call fzp_propagate_roi_range is the one-GPU share).", file=sys.stderr)
+        print("bench.py measures one GPU only; a multi-GPU job gives each GPU a range of aperture rows "
+              "(fzp_propagate_roi_range) and sums the ROIs.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -58,7 +58,7 @@ typedef int32_t fzp_status_t;
 #define FZP_E_SAMPLING (-2)    /* pitch coarser than the Nyquist limit of Eq. 6 */
 #define FZP_E_NOMEM (-3)       /* workspace larger than the caller's limit */
 #define FZP_E_DEVICE (-4)      /* a HIP call failed */
-#define FZP_E_UNSUPPORTED (-5) /* valid but outside what this build handles */
+#define FZP_E_UNSUPPORTED (-5) /* valid, but outside what the library handles */
 
 /* Row-pass evaluation path. */
 #define FZP_PATH_FP64_BLUESTEIN 0 /* Bluestein CZT per row, float64 throughout (Sec. 2.6) */
