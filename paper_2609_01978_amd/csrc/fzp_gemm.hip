@@ -17,6 +17,7 @@
 // operand (8 consecutive k of one column) is one 16-byte chunk, and the
 // accumulator columns interleave re/im as the float2 T buffer does.
 
+#include <atomic>
 #include <cmath>
 
 #include "fzp_split.h"
@@ -406,8 +407,10 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
 }  // namespace
 
 hipError_t init_split_attributes() {
-  static bool done = false;  // set once per process (the attributes are per function)
-  if (done) return hipSuccess;
+  // set once per process (the attributes belong to the functions); threads
+  // racing through the first call all set the same values
+  static std::atomic<bool> done{false};
+  if (done.load(std::memory_order_acquire)) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split<4, 4, false, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, BinTile<4, 4>::lds);
   if (e == hipSuccess)
@@ -423,7 +426,7 @@ hipError_t init_split_attributes() {
     e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<2, 4>::lds);
   if (e == hipSuccess) e = init_cplx_attributes();
-  if (e == hipSuccess) done = true;
+  if (e == hipSuccess) done.store(true, std::memory_order_release);
   return e;
 }
 
