@@ -167,7 +167,7 @@ __device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
 
 // Row-pass GEMM for complex stripes.  Work-group tile: kCTR aperture rows x
 // kCTC real columns of T over one K segment (trimmed to the tiles' disc
-// chord).  8 waves in a 2 (rows) x 4 (columns) grid, each 128 x 64 = 4 x 2
+// chord).  8 waves in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4
 // MFMA 32x32 blocks (128 float32 accumulators per lane), 6 MFMAs per block
 // per K-step.  Stripe and table slabs move HBM -> LDS by direct copies into a
 // 3-deep ring, 2 stages ahead, one barrier per stage.
@@ -227,19 +227,21 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
     bsrc[j] = d.A + (int64_t)(y >> 3) * M2 * d.Npad + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
   }
 
-  // ---- compute role: wave (wr, wc) covers rows wr*128 .., columns wc*64 ..
-  const int wr = wave >> 2, wc = wave & 3;
+  // ---- compute role: wave (wr, wc) covers rows wr*64 .., columns wc*128 ..
+  // (2 x 4 MFMA blocks: each stripe operand read from LDS feeds four column
+  // blocks)
+  const int wr = wave >> 1, wc = wave & 1;
   const int l32 = lane & 31, lhi = lane >> 5;
   const int hofs = chalf(l32, lhi) * 16;
-  const int aoff = (wr * 128 + l32) * kCRowB + hofs;
-  const int boff = kCGBytes + (wc * 64 + l32) * kCRowB + hofs;
+  const int aoff = (wr * 64 + l32) * kCRowB + hofs;
+  const int boff = kCGBytes + (wc * 128 + l32) * kCRowB + hofs;
   const uint32_t nmask = (lane & 1) ? 0u : 0x80008000u;
 
-  f32x16 acc[4][2];
+  f32x16 acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
@@ -269,33 +271,33 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
     for (int s = 0; s < nst; ++s) {
       copy_stage(s + kCAhead);
       const char *sb = lds + (s % kCRing) * kCStage;
-      bf16x8 bh[2], bl[2], bhs[2], bls[2];
+      bf16x8 bh[4], bl[4], bhs[4], bls[4];
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
+      for (int cb = 0; cb < 4; ++cb) {
         bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB));
         bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB + kCTC * kCRowB));
         bhs[cb] = swap_neg(bh[cb], nmask);
         bls[cb] = swap_neg(bl[cb], nmask);
       }
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
+      for (int rb = 0; rb < 2; ++rb) {
         const char *pa = sb + aoff + rb * 32 * kCRowB;
         const bf16x8 rh = __builtin_bit_cast(bf16x8, lds_ld16(pa));
         const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
         const bf16x8 ih = __builtin_bit_cast(bf16x8, lds_ld16(pa + 2 * kCTR * kCRowB));
         const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bh[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bhs[cb], acc[rb][cb], 0, 0, 0);
         }
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bls[cb], acc[rb][cb], 0, 0, 0);
         }
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
         }
@@ -304,8 +306,30 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
-  store_partials(acc, T + (int64_t)(seg - seg_lo) * seg_stride_f, seg_stride_f / M2, c0 + wc * 64 + l32, M2,
-                 r0 + wr * 128 + 4 * lhi, row_begin, row_end);
+  // epilogue: register v of lane l holds row 8(v/4) + 4(l/32) + (v%4) of its
+  // block and column l%32; partials column-major per real column
+  float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
+  const int64_t rs = seg_stride_f / M2;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int c = c0 + wc * 128 + cb * 32 + l32;
+    if (c >= M2) continue;
+    float *col = Ts + (int64_t)c * rs - row_begin;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r = r0 + wr * 64 + 4 * lhi + rb * 32 + 8 * a;
+        if (r + 3 < row_end) {
+          *(float4 *)(col + r) = make_float4(acc[rb][cb][4 * a], acc[rb][cb][4 * a + 1], acc[rb][cb][4 * a + 2],
+                                             acc[rb][cb][4 * a + 3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r + e < row_end) col[r + e] = acc[rb][cb][4 * a + e];
+        }
+      }
+  }
 }
 
 }  // namespace
