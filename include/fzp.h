@@ -111,7 +111,11 @@ typedef struct {
 typedef struct {
   int32_t path;         /* FZP_PATH_* */
   int32_t stripe_rows;  /* rows per stripe, the row-pass work unit; 0 = path default */
-  int64_t chunk_rows;   /* rows transformed between two column passes; 0 = automatic */
+  int64_t chunk_rows;   /* rows transformed between two column passes; 0 = automatic: the
+                           row-pass partial sums near 1 GiB (split) or 0.5 GiB (FP64); for
+                           creased instances on the split path the complex stripe planes
+                           near 2 GiB, grown up to 8 GiB while the GEMM grid of the
+                           smallest ROI has fewer than 512 tiles */
   uint64_t workspace_limit; /* bytes; 0 = no limit.  fzp_plan fails with FZP_E_NOMEM
                                if the workspace would exceed it */
   int32_t flags;        /* FZP_FLAG_* */
