@@ -55,6 +55,36 @@ constexpr int kCLdsBytes = kCRing * kCStage;  // 147456
 // 16 so that 16 consecutive rows read at one half hit 64 distinct banks.
 __device__ __forceinline__ int chalf(int row, int half) { return half ^ ((row >> 3) & 1); }
 
+// sin and cos of 2 pi t (t in turns, |t| up to a few hundred) in float32:
+// t is cut into a quarter-turn count q and a remainder r in [-1/2, 1/2]
+// quarter turns, sin and cos of the angle r pi/2 (at most pi/4) come from
+// their Taylor series through the x^9 and x^10 terms (truncation below
+// 3e-9), and q mod 4 rotates the pair.  Enough for the BF16 hi/lo pair the
+// stripe keeps (16 significant bits).
+__device__ __forceinline__ void sincos_turns(float t, float &sn, float &cs) {
+  const float u = 4.0f * t;
+  const float q = rintf(u);
+  const float x = (u - q) * 1.57079632679489662f;
+  const float x2 = x * x;
+  float ps = fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = fmaf(x2, ps, 1.0f / 120.0f);
+  ps = fmaf(x2, ps, -1.0f / 6.0f);
+  const float sx = fmaf(x * x2, ps, x);
+  float pc = fmaf(x2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  pc = fmaf(x2, pc, -1.0f / 720.0f);
+  pc = fmaf(x2, pc, 1.0f / 24.0f);
+  pc = fmaf(x2, pc, -0.5f);
+  const float cx = fmaf(x2, pc, 1.0f);
+  const int k = (int)q & 3;  // angle = x + k pi/2
+  const float a = (k & 1) ? cx : sx, b = (k & 1) ? sx : cx;
+  sn = (k & 2) ? -a : a;
+  cs = ((k + 1) & 2) ? -b : b;
+}
+
+// Round to nearest even into BF16 by the hardware conversion (one
+// instruction; the same result as the integer rounding of the operand table).
+__device__ __forceinline__ uint16_t bf16_cvt(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
 __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
                                                      int64_t rows_pad, int64_t kb0, int64_t nkb,
                                                      uint16_t *__restrict__ G) {
@@ -130,15 +160,13 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
       uint32_t pr[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        float t = turns[e + u];
-        t -= rintf(t);
         float sn, cs;
-        sincospif(2.0f * t, &sn, &cs);
+        sincos_turns(turns[e + u], sn, cs);
         const bool o = (open >> (e + u)) & 1u;
         const float gr = o ? cs : 0.0f, gi = o ? sn : 0.0f;
-        const uint16_t rh = bf16_rne(gr), ih = bf16_rne(gi);
-        const uint16_t rlo = bf16_rne(gr - __uint_as_float((uint32_t)rh << 16));
-        const uint16_t ilo = bf16_rne(gi - __uint_as_float((uint32_t)ih << 16));
+        const uint16_t rh = bf16_cvt(gr), ih = bf16_cvt(gi);
+        const uint16_t rlo = bf16_cvt(gr - __uint_as_float((uint32_t)rh << 16));
+        const uint16_t ilo = bf16_cvt(gi - __uint_as_float((uint32_t)ih << 16));
         pr[0] |= (uint32_t)rh << (16 * u);
         pr[1] |= (uint32_t)rlo << (16 * u);
         pr[2] |= (uint32_t)ih << (16 * u);
