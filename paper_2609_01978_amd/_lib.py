@@ -3,8 +3,10 @@
 Argument marshalling only: every step of the propagation and of the metric
 extraction runs in the library's HIP kernels.  PyTorch supplies device memory
 and the current HIP stream.  The library must be built
-(``python -m paper_2609_01978_amd.build``); importing this module fails loudly
-when it is missing.
+(``python -m paper_2609_01978_amd.build``); the first call that needs it
+raises ImportError when it is missing (there is no other implementation to
+fall back to).  It is loaded on first use so that the build step itself can
+import the package.
 """
 from __future__ import annotations
 
