@@ -143,3 +143,15 @@ def test_mlp_create_and_layout():
     for bad in ((0, 512, 16384, 256), (33, 512, 16384, 0), (33, 0, 10, 1), (33, 10, 10, 70000)):
         assert lib.fzp_mlp_create(*bad, ctypes.byref(h)) == P.FZP_E_INVAL
     assert b"sizes" in lib.fzp_last_error()
+
+
+def test_missing_library_raises_import_error(monkeypatch):
+    """No other implementation exists: without libfzp.so the first call that needs
+    it raises ImportError."""
+    from paper_2609_01978_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", L.LIB_PATH + ".absent")
+    with pytest.raises(ImportError):
+        L.load_library()
+    with pytest.raises(ImportError):
+        P.Plan(dict(D=2e-3, f0=10e-3, lambda0=632.8e-9, N=256), [dict(lam=632.8e-9, M=16)])
