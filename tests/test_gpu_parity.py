@@ -419,3 +419,47 @@ def test_largest_aperture_sampled_stripe(path):
     e = rel_l2(U, ref)
     announce(f"  complex rel-L2 {e:.3e}")
     assert e <= (1e-6 if path == "fp64" else 1e-4)
+
+
+# ---------------------------------------------------------------------------
+# Seeded random shapes: both paths, every binary GEMM variant, creased or not
+# ---------------------------------------------------------------------------
+
+def _random_cases(n=16, seed=2026):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cases = []
+    for k in range(n):
+        N = int(rng.integers(64, 3200))
+        D = float(rng.uniform(0.5e-3, 3e-3))
+        f0 = D * float(rng.uniform(3.0, 8.0))
+        M = 16 * int(rng.integers(1, 17))                # 16 .. 256, the split path's multiples of 16
+        ap = dict(D=D, f0=f0, lambda0=LAM0, N=N, centre_open=int(rng.integers(0, 2)))
+        if rng.random() < 0.3:
+            ap["pitch"] = D / (N - int(rng.integers(0, 8)))   # disc slightly smaller than the grid
+        lam = float(rng.uniform(500e-9, 800e-9))
+        hw = 8 * lam * (f0 * LAM0 / lam) / D
+        inst = dict(lam=lam, M=M, x0=float(rng.uniform(-0.3, 0.3)) * hw, y0=float(rng.uniform(-0.3, 0.3)) * hw,
+                    half_width=hw * float(rng.uniform(0.5, 1.5)))
+        if rng.random() < 0.4:
+            inst["creases"] = crease_draws(int(rng.integers(0, 1000)), D, LAM0, int(rng.integers(1, 9)))
+        cases.append((k, ap, inst, int(rng.integers(0, 5))))
+    return cases
+
+
+@pytest.mark.parametrize("case", _random_cases(), ids=lambda c: f"r{c[0]}")
+def test_random_shapes_both_paths(case):
+    k, ap, inst, variant = case
+    announce(f"random case {k}: N={ap['N']} M={inst['M']} creases={len(inst.get('creases', []))} variant {variant}")
+    _, _, _, (U64,) = run_gpu(ap, [inst], allow_undersampled=True)
+    _, _, _, (Us,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, variant=variant)
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=256)
+    Iref = O.intensity(ref)
+    if np.linalg.norm(Iref) == 0.0:
+        assert np.abs(U64).max() == 0.0 and np.abs(Us).max() == 0.0
+        return
+    e64 = rel_l2(U64, ref)
+    es = rel_l2(O.intensity(Us), Iref)
+    announce(f"  fp64 complex rel-L2 {e64:.2e}, split intensity rel-L2 {es:.2e}")
+    assert e64 < 1e-9
+    assert es <= 1e-4
