@@ -69,9 +69,9 @@ def kernel_sources_sha256(kernel_srcs) -> str:
     return h.hexdigest()
 
 
-def committed_traffic(kernel_srcs, summary: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernel sources changed since the counters were taken."""
+def committed_value(kernel_srcs, summary: str, key: str):
+    """A `key: value` figure from a committed rocprofv3 summary, or None when the
+    kernel sources changed since its counters were taken."""
     here = os.path.dirname(os.path.abspath(__file__))
     try:
         text = open(os.path.join(here, summary)).read()
@@ -79,9 +79,15 @@ def committed_traffic(kernel_srcs, summary: str):
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("|", "#")))
-    if vals.get("kernel_source_sha256", "").strip() != digest:
+    if vals.get("kernel_source_sha256", "").strip() != digest or key not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
+
+
+def committed_traffic(kernel_srcs, summary: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since the counters were taken."""
+    return committed_value(kernel_srcs, summary, "traffic_bytes_per_launch")
 
 
 def bluestein_blocks(N: int, B: int) -> int:
@@ -245,9 +251,14 @@ def main():
     achieved = flops_step / (row_ms_step * 1e-3) / 1e12
     traffic = committed_traffic(GEMM_SOURCES, "profiles/hbm_traffic_k_row_pass_split_fzp1m.md") \
         if args.workload == "fzp1m" else None
+    # matrix-core busy share of the kernel's cycles (SQ counters): with the
+    # clock under load it accounts for the gap between `frac` and 1
+    mfma_busy = committed_value(GEMM_SOURCES, "profiles/sq_counters_k_row_pass_split_fzp1m.md",
+                                "mfma_busy_fraction_of_cycles") if args.workload == "fzp1m" else None
     roofline = dict(bound="mfma", achieved=round(achieved, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
                     traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    mfma_busy=mfma_busy,
                     kernel="k_row_pass_split",
                     launch_ms=round(pr["row_ms"] / max(pr["row_launches"], 1), 3),
                     launches_per_step=launches_per_step,

@@ -40,5 +40,6 @@ def test_json_line_at_the_small_workload():
     assert ro["bound"] == "mfma" and ro["unit"] == "TFLOP/s" and ro["peak"] == 2500.0
     assert 0 < ro["achieved"] < ro["peak"] and abs(ro["frac"] - ro["achieved"] / ro["peak"]) < 1e-3
     assert ro["traffic"] is None            # the committed counters cover the 1 m workload only
+    assert ro["mfma_busy"] is None
     assert d["valid_rel_l2_le_1e-4"] is True and d["rel_l2_split_vs_fp64"] <= 1e-4
     assert d["fp64_bluestein"]["roofline"]["bound"] == "alu"
