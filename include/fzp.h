@@ -60,11 +60,13 @@ typedef int32_t fzp_status_t;
 #define FZP_E_DEVICE (-4)      /* a HIP call failed */
 #define FZP_E_UNSUPPORTED (-5) /* valid, but outside what the library handles */
 
-/* Row-pass evaluation path. */
-#define FZP_PATH_FP64_BLUESTEIN 0 /* Bluestein CZT per row, float64 throughout (Sec. 2.6) */
-#define FZP_PATH_SPLIT_BF16 1     /* row pass as a BF16 MFMA complex GEMM with hi/lo split
-                                     operands and float32 accumulation; column pass and
-                                     the ROI sum in float64 */
+/* Evaluation path of the two CZT passes (Eqs. 9-10). */
+#define FZP_PATH_FP64_BLUESTEIN 0 /* Bluestein CZT per row and per ROI column, float64
+                                     throughout (Sec. 2.6) */
+#define FZP_PATH_SPLIT_BF16 1     /* both passes as BF16 MFMA complex GEMMs (stripe . A_x^T,
+                                     then B_y . T) with hi/lo split operands and float32
+                                     accumulation; phases, the sums over K segments and
+                                     chunks and the ROI in float64 */
 
 /* Plan flags. */
 #define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */
@@ -153,7 +155,7 @@ fzp_status_t fzp_roi_elements(fzp_plan_t p, int64_t *n_complex);
 fzp_status_t fzp_roi_offset(fzp_plan_t p, int32_t k, int64_t *offset_complex);
 
 /* Build the plan's device tables (Bluestein chirps and filter spectra, the
- * split-path operand tables) inside `workspace`.  Asynchronous on `stream`.
+ * split-path kernel matrices A_x and B_y) inside `workspace`.  Asynchronous on `stream`.
  * fzp_propagate_roi calls it itself when given a workspace it has not seen. */
 fzp_status_t fzp_prepare(fzp_plan_t p, void *workspace, void *stream);
 

@@ -195,16 +195,19 @@ __device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
 
 // Row-pass GEMM for complex stripes.  Work-group tile: kCTR aperture rows x
 // kCTC real columns of T over one K segment (trimmed to the tiles' disc
-// chord).  8 waves in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4
+// chord).  With COL the same kernel is the column pass of the split path:
+// rows are ROI rows p, K is the chunk's aperture rows j (segments of
+// seg_len_c rows, no chord), the A operand the column kernel matrix B_y and
+// the B operand the chunk's row-pass result T (see k_col_operand).  8 waves in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4
 // MFMA 32x32 blocks (128 float32 accumulators per lane), 6 MFMAs per block
 // per K-step.  Stripe and table slabs move HBM -> LDS by direct copies into a
 // 3-deep ring, 2 stages ahead, one barrier per stage.
-__global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d, int64_t row_begin,
-                                                                     int64_t row_end, int n_rt, int n_ct,
-                                                                     int seg_lo, int n_seg,
-                                                                     const uint16_t *__restrict__ G,
-                                                                     int64_t rows_pad, int64_t kb0, int64_t nkb,
-                                                                     float *__restrict__ T, int64_t seg_stride_f) {
+template <bool COL>
+__global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
+    InstDev d, int64_t row_begin, int64_t row_end, int n_rt, int n_ct, int seg_lo, int n_seg,
+    const uint16_t *__restrict__ G, int64_t rows_pad, int64_t kb0, int64_t nkb, float *__restrict__ T,
+    int64_t seg_stride_f, const uint16_t *__restrict__ Bop, int64_t kB0, int64_t KB, int64_t k_begin, int64_t k_end,
+    int64_t seg_len_c) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -222,16 +225,21 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
   int64_t rl = r0 + kCTR - 1;
   if (rl > row_end - 1) rl = row_end - 1;
   const int c0 = ct * kCTC;
-  const int64_t s_lo = (int64_t)seg * d.seg_len;
-  const int64_t s_hi = s_lo + d.seg_len < d.Npad ? s_lo + d.seg_len : d.Npad;
   int64_t k_lo, k_hi;
-  tile_chord(d, r0, rl, k_lo, k_hi);
-  k_lo = k_lo / kCKT * kCKT;
-  k_hi = (k_hi + kCKT - 1) / kCKT * kCKT;
-  if (k_lo < s_lo) k_lo = s_lo;
-  if (k_hi > s_hi) k_hi = s_hi;
-  if (k_lo < 16 * kb0) k_lo = 16 * kb0;
-  if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
+  if constexpr (COL) {
+    k_lo = k_begin + (int64_t)(seg - seg_lo) * seg_len_c;
+    k_hi = k_lo + seg_len_c < k_end ? k_lo + seg_len_c : k_end;
+  } else {
+    const int64_t s_lo = (int64_t)seg * d.seg_len;
+    const int64_t s_hi = s_lo + d.seg_len < d.Npad ? s_lo + d.seg_len : d.Npad;
+    tile_chord(d, r0, rl, k_lo, k_hi);
+    k_lo = k_lo / kCKT * kCKT;
+    k_hi = (k_hi + kCKT - 1) / kCKT * kCKT;
+    if (k_lo < s_lo) k_lo = s_lo;
+    if (k_hi > s_hi) k_hi = s_hi;
+    if (k_lo < 16 * kb0) k_lo = 16 * kb0;
+    if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
+  }
 
   // ---- copy roles.  Stripe: wave w copies slab pieces x = 4w .. 4w+3 (plane
   // x / 8, rows 32 (x % 8) ..); table: pieces y = 2w, 2w+1 (plane y / 8,
@@ -252,7 +260,7 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
     const int y = 2 * wave + j;
     const int col = (y & 7) * 32 + (lane >> 1);
     const int gc = c0 + col < M2 ? c0 + col : 0;
-    bsrc[j] = d.A + (int64_t)(y >> 3) * M2 * d.Npad + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
+    bsrc[j] = Bop + (int64_t)(y >> 3) * M2 * KB + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
   }
 
   // ---- compute role: wave (wr, wc) covers rows wr*64 .., columns wc*128 ..
@@ -286,7 +294,8 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
         __builtin_amdgcn_global_load_lds((const void *)(gsrc[j] + gofs),
                                          (__attribute__((address_space(3))) void *)(dst + (4 * wave + j) * 1024),
                                          16, 0, 0);
-      const int64_t bofs = (k >> 5) * M2 * 32 + (k & 31);
+      const int64_t kr = k - kB0;  // K index of the B operand's blocked layout
+      const int64_t bofs = (kr >> 5) * M2 * 32 + (kr & 31);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         __builtin_amdgcn_global_load_lds((const void *)(bsrc[j] + bofs),
@@ -335,8 +344,27 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   // epilogue: register v of lane l holds row 8(v/4) + 4(l/32) + (v%4) of its
-  // block and column l%32; partials column-major per real column
+  // block and column l%32.  Row pass: partials column-major per real column;
+  // column pass: row-major (ROI row p, real column c), so that the finishing
+  // kernel reads and writes along ROI rows.
   float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
+  if constexpr (COL) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int c = c0 + wc * 128 + cb * 32 + l32;
+      if (c >= M2) continue;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t r = r0 + wr * 64 + 4 * lhi + rb * 32 + 8 * a + e;
+            if (r < row_end) Ts[r * M2 + c] = acc[rb][cb][4 * a + e];
+          }
+    }
+    return;
+  }
   const int64_t rs = seg_stride_f / M2;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
@@ -360,11 +388,110 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(InstDev d,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column pass of the split path (B_y . T, Eqs. 9-10 along y): per chunk of
+// aperture rows j, C[p][q] = sum_j B_y[p][j] T[j][q] with
+//   B_y[p][j] = exp(2 pi i (beta c_j^2 / 2 - alpha c_j d_p)),
+//   c_j = j - (N-1)/2, d_p = p - M/2 + s_y,
+// on the matrix cores with the same three-product BF16 split and float32
+// accumulation per K segment; the segments and the chunks are added in
+// float64 into the ROI together with the output factor of Eq. 2.
+// ---------------------------------------------------------------------------
+
+// B_y in the stripe-plane layout G[v][j/16][p][16] (v = re_hi, re_lo, im_hi,
+// im_lo), p padded to the 256-row tile, j to Npad; zero outside p < M, j < N.
+__global__ __launch_bounds__(256) void k_build_col_table(InstDev d, int64_t rows_pad, uint16_t *__restrict__ By) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t p = blockIdx.y;
+  if (j >= d.Npad) return;
+  const int M = d.M;
+  uint16_t hr = 0, hi_ = 0, lr = 0, li = 0;
+  if (j < d.N && p < M) {
+    const double c = (double)j - 0.5 * (double)(d.N - 1);
+    const double dp = (double)p - 0.5 * (double)M + d.sy;
+    const double ph = 0.5 * d.beta * (c * c);
+    const double lin = d.alpha * c * dp;
+    const double2 a = cexp_turns((ph - rint(ph)) - (lin - rint(lin)));
+    hr = bf16_rne((float)a.x);
+    hi_ = bf16_rne((float)a.y);
+    lr = bf16_rne((float)(a.x - (double)__uint_as_float((uint32_t)hr << 16)));
+    li = bf16_rne((float)(a.y - (double)__uint_as_float((uint32_t)hi_ << 16)));
+  }
+  const int64_t plane = (d.Npad / 16) * rows_pad * 16;
+  const int64_t at = ((j >> 4) * rows_pad + p) * 16 + (j & 15);
+  By[at] = hr;
+  By[plane + at] = lr;
+  By[2 * plane + at] = hi_;
+  By[3 * plane + at] = li;
+}
+
+// T of the chunk (float32 partial planes, one per K segment of the row pass,
+// column-major per real column, summed here in float64) as the column GEMM's
+// B operand: BF16 hi and lo planes in the operand-table layout
+// Tb[h][kk/32][c][kk%32], kk = j - kB0 for j in [kB0, kB0 + KB); zero for rows
+// outside [row_begin, row_end).  A work-group covers one 32-row block of kk and
+// 8 columns, so each wave reads two 128-byte runs of T and writes one
+// 128-byte run per plane (one 512-byte run per work-group).
+__global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, int64_t row_end,
+                                                     const float *__restrict__ T, int nseg, int64_t seg_stride_f,
+                                                     int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb) {
+  const int64_t kk = blockIdx.x * (int64_t)32 + (threadIdx.x & 31);
+  const int c = blockIdx.y * 8 + (threadIdx.x >> 5);
+  if (kk >= KB || c >= M2) return;
+  const int64_t j = kB0 + kk;
+  uint16_t h = 0, l = 0;
+  if (j >= row_begin && j < row_end) {
+    const float *src = T + (int64_t)c * rs + (j - row_begin);
+    double v = 0.0;
+    int sgi = 0;
+    for (; sgi + 4 <= nseg; sgi += 4) {
+      const float a0 = src[(int64_t)sgi * seg_stride_f], a1 = src[(int64_t)(sgi + 1) * seg_stride_f];
+      const float a2 = src[(int64_t)(sgi + 2) * seg_stride_f], a3 = src[(int64_t)(sgi + 3) * seg_stride_f];
+      v += (double)a0;
+      v += (double)a1;
+      v += (double)a2;
+      v += (double)a3;
+    }
+    for (; sgi < nseg; ++sgi) v += (double)src[(int64_t)sgi * seg_stride_f];
+    h = bf16_rne((float)v);
+    l = bf16_rne((float)(v - (double)__uint_as_float((uint32_t)h << 16)));
+  }
+  const int64_t at = (kk >> 5) * (int64_t)M2 * 32 + (int64_t)c * 32 + (kk & 31);
+  Tb[at] = h;
+  Tb[(int64_t)M2 * KB + at] = l;
+}
+
+// ROI[p][q] += F[p][q] sum_seg C_seg[p][q] (float64), F the output factor of
+// Eq. 2; C_seg row-major with re/im adjacent: C[seg][p][2q + {0, 1}].
+__global__ __launch_bounds__(256) void k_col_finish(InstDev d, const float *__restrict__ C, int nseg,
+                                                    int64_t segC, double2 *__restrict__ roi) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  const int M = d.M;
+  if (q >= M) return;
+  const float2 *src = (const float2 *)(C + (int64_t)p * (2 * M)) + q;
+  float2 v = src[0];
+  double2 acc = make_double2((double)v.x, (double)v.y);
+  for (int sgi = 1; sgi < nseg; ++sgi) {
+    v = src[(int64_t)sgi * (segC / 2)];
+    acc = cadd(acc, make_double2((double)v.x, (double)v.y));
+  }
+  const double xq = d.x0 + ((double)q - 0.5 * (double)M) * d.dx_out;
+  const double yp = d.y0 + ((double)p - 0.5 * (double)M) * d.dx_out;
+  const double2 F = cscale(cexp_turns(d.kz_turns + (xq * xq + yp * yp) * d.inv2lz), d.scale);
+  double2 *o = roi + (int64_t)p * M + q;
+  *o = cadd(*o, cmul(F, acc));
+}
+
 }  // namespace
 
 hipError_t init_cplx_attributes() {
-  return hipFuncSetAttribute((const void *)k_row_pass_split_cplx, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             kCLdsBytes);
+  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kCLdsBytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kCLdsBytes);
+  return e;
 }
 
 size_t split_stripe_bytes(const InstDev &d, int64_t chunk_rows) {
@@ -414,8 +541,89 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
   const int64_t grid = (Gn + 255) / 256 * 256;
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_pass_split_cplx, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d, row_begin,
-                     row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride);
+  hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
+                     row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride,
+                     d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+
+// Column pass of the split path: K extent and segments of one chunk.
+namespace {
+struct ColSchedule {
+  int64_t kB0, KB, k_begin, k_end, seg_len;
+  int n_rt, n_ct, n_seg;
+};
+ColSchedule col_schedule(int M, int64_t row_begin, int64_t row_end) {
+  ColSchedule c;
+  c.kB0 = row_begin / 32 * 32;
+  c.k_begin = row_begin / 16 * 16;
+  c.k_end = (row_end + 15) / 16 * 16;
+  c.KB = (c.k_end - c.kB0 + 31) / 32 * 32;
+  c.n_rt = (M + kCTR - 1) / kCTR;
+  c.n_ct = (2 * M + kCTC - 1) / kCTC;
+  // about 512 tiles in all, segments of at least 256 rows
+  const int64_t target = (512 + c.n_rt * c.n_ct - 1) / (c.n_rt * c.n_ct);
+  const int64_t rows = c.k_end - c.k_begin;
+  int64_t len = (rows + target - 1) / target;
+  len = (len + 15) / 16 * 16;
+  if (len < 256) len = 256;
+  c.seg_len = len;
+  c.n_seg = rows > 0 ? (int)((rows + len - 1) / len) : 0;
+  return c;
+}
+}  // namespace
+
+size_t col_table_bytes(int M, int64_t Npad) {
+  const int64_t rows_pad = (M + kCTR - 1) / kCTR * kCTR;
+  return (size_t)4 * (size_t)Npad * (size_t)rows_pad * sizeof(uint16_t);
+}
+
+size_t col_operand_bytes(int M, int64_t chunk_rows) {
+  // the K extent runs from row_begin rounded down to 32 to row_end rounded
+  // up to 16: at most chunk_rows + 47 rows, rounded up to 32
+  const int64_t KB = (chunk_rows + 47 + 31) / 32 * 32;
+  return (size_t)2 * (size_t)KB * (size_t)(2 * M) * sizeof(uint16_t);
+}
+
+size_t col_partial_bytes(int M) {
+  // a chunk gets at most `target` segments (seg_len >= rows / target)
+  const ColSchedule c = col_schedule(M, 0, 0);
+  const int64_t target = (512 + c.n_rt * c.n_ct - 1) / (c.n_rt * c.n_ct);
+  return (size_t)target * (size_t)M * (size_t)(2 * M) * sizeof(float);
+}
+
+hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st) {
+  const int64_t rows_pad = (d.M + kCTR - 1) / kCTR * kCTR;
+  const dim3 grid((unsigned)((d.Npad + 255) / 256), (unsigned)rows_pad);
+  hipLaunchKernelGGL(k_build_col_table, grid, dim3(256), 0, st, d, rows_pad, By);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
+                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st) {
+  if (row_end <= row_begin || nseg <= 0) return hipSuccess;
+  const int M = d.M, M2 = 2 * M;
+  const ColSchedule c = col_schedule(M, row_begin, row_end);
+  // T -> BF16 hi/lo operand (the row-pass partial planes: column stride = chunk rows)
+  const int64_t rs = seg_stride / M;
+  hipLaunchKernelGGL(k_col_operand, dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
+                     row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = init_split_attributes();
+  if (e != hipSuccess) return e;
+  const int64_t rows_pad = (M + kCTR - 1) / kCTR * kCTR;
+  const int64_t Gn = (int64_t)c.n_rt * c.n_ct * c.n_seg;
+  const int64_t grid = (Gn + 255) / 256 * 256;
+  const int64_t segC = (int64_t)M * M2;  // floats per partial plane
+  hipLaunchKernelGGL(k_row_pass_split_cplx<true>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
+                     (int64_t)0, (int64_t)M, c.n_rt, c.n_ct, 0, c.n_seg, d.By, rows_pad, (int64_t)0, d.Npad / 16, C,
+                     segC, (const uint16_t *)Tb, c.kB0, c.KB, c.k_begin, c.k_end, c.seg_len);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_finish, dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st, d,
+                     (const float *)C, c.n_seg, segC, roi);
   return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ struct InstDev {
   const double2 *Qx, *Qy;  // e^{-i pi alpha d^2}
   const CreaseDev *cr;
   const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
+  const uint16_t *By;      // split path: column kernel matrix, [4 planes][Npad/16][M padded to 256][16] bf16
   int64_t Npad;
   int64_t seg_len;         // split path: K columns per float32 partial sum (power of two)
   int32_t bin_tile_rows;   // split path, binary stripes: GEMM tile rows (512 or 256)
@@ -65,9 +66,10 @@ struct InstHost {
   std::vector<fzp_crease_t> creases;
   double lam, z, hw, dx_out;
   InstDev dev;
-  size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A;
+  size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A, off_By;
   int64_t roi_off;     // complex elements
   int32_t table_owner; // instance whose split table this one shares (itself if none)
+  int32_t col_owner;   // instance whose column table (B_y) this one shares (itself if none)
 };
 
 struct Plan {
@@ -84,8 +86,8 @@ struct Plan {
   int64_t roi_elems;
   // stripe buffers, one set per lane: row-pass result T, zone-mask bits and
   // complex stripe planes (split path)
-  size_t T_bytes = 0, bits_bytes = 0, G_bytes = 0;
-  std::vector<size_t> off_T, off_bits, off_G;
+  size_t T_bytes = 0, bits_bytes = 0, G_bytes = 0, Tb_bytes = 0, C_bytes = 0;
+  std::vector<size_t> off_T, off_bits, off_G, off_Tb, off_C;
   int32_t lanes_max = 1, lanes = 1;
   int64_t seg_len = 0;  // split path K segment (all instances)
   int32_t bin_variant = 4;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring,
@@ -138,6 +140,16 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
                                  float2 *T, int64_t seg_stride, const uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,
                            bool t_is_fp32, int nseg, int64_t seg_stride, double2 *roi, hipStream_t st);
+// Split path column pass as a split-BF16 GEMM (fzp_cplx.hip): the column kernel
+// matrix B_y (col_table_bytes, built once per workspace), the chunk's T as a
+// BF16 hi/lo operand (col_operand_bytes per lane) and float32 partial planes
+// of the product (col_partial_bytes per lane), added in float64 into the ROI.
+size_t col_table_bytes(int M, int64_t Npad);
+size_t col_operand_bytes(int M, int64_t chunk_rows);
+size_t col_partial_bytes(int M);
+hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st);
+hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
+                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st);
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,
                           fzp_metrics_t *dev_out, hipStream_t st);
 size_t metrics_scratch_bytes(int32_t M);

@@ -295,7 +295,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       ih.off_cr = off;
       off = align256(off + (size_t)(ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
       ih.table_owner = k;
+      ih.col_owner = k;
       ih.off_A = 0;
+      ih.off_By = 0;
     }
     if (split) {
       const int64_t npad = (N + 63) / 64 * 64;
@@ -315,6 +317,20 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
           ih.off_A = off;
           off = align256(off + (size_t)2 * 2 * ih.in.M * npad * sizeof(uint16_t));
         }
+        // the column pass's kernel matrix B_y: shared on the same terms, with the y shift
+        for (int k2 = 0; k2 < k; ++k2) {
+          const InstHost &o2 = p.inst[k2];
+          if (o2.col_owner == k2 && o2.dev.M == ih.dev.M && o2.dev.alpha == ih.dev.alpha &&
+              o2.dev.beta == ih.dev.beta && o2.dev.sy == ih.dev.sy) {
+            ih.col_owner = k2;
+            ih.off_By = o2.off_By;
+            break;
+          }
+        }
+        if (ih.col_owner == k) {
+          ih.off_By = off;
+          off = align256(off + fzp::col_table_bytes(ih.in.M, npad));
+        }
         ih.dev.Npad = npad;
       }
     }
@@ -322,6 +338,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     if (split) {
       p.bits_bytes = align256(fzp::split_bits_bytes(p.inst[0].dev, p.chunk_rows));
       if (cplx) p.G_bytes = align256(fzp::split_stripe_bytes(p.inst[0].dev, p.chunk_rows));
+      for (const auto &ih : p.inst) {
+        p.Tb_bytes = std::max(p.Tb_bytes, align256(fzp::col_operand_bytes(ih.in.M, p.chunk_rows)));
+        p.C_bytes = std::max(p.C_bytes, align256(fzp::col_partial_bytes(ih.in.M)));
+      }
     }
     for (int l = 0; l < p.lanes_max; ++l) {
       p.off_T.push_back(off);
@@ -332,6 +352,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       off += nbuf * p.bits_bytes;
       p.off_G.push_back(off);
       off += nbuf * p.G_bytes;
+      p.off_Tb.push_back(off);
+      off += p.Tb_bytes;
+      p.off_C.push_back(off);
+      off += p.C_bytes;
     }
     p.off_scratch = off;
     p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
@@ -403,6 +427,7 @@ void bind_tables(Plan &p, char *ws) {
     ih.dev.Qy = (const double2 *)(ws + ih.off_Qy);
     ih.dev.cr = (const fzp::CreaseDev *)(ws + ih.off_cr);
     ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
+    ih.dev.By = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_By) : nullptr;
   }
 }
 
@@ -440,6 +465,10 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
       if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.table_owner == (int32_t)k) {
         e = fzp::launch_build_split_table(p, ih, ws, st);
         if (e != hipSuccess) return hip_fail("fzp_prepare: split table kernel", e);
+      }
+      if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.col_owner == (int32_t)k) {
+        e = fzp::launch_build_col_table(ih.dev, (uint16_t *)(ws + ih.off_By), st);
+        if (e != hipSuccess) return hip_fail("fzp_prepare: column table kernel", e);
       }
     }
     if (p.opt.path == FZP_PATH_SPLIT_BF16) {
@@ -600,7 +629,11 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     if (e == hipSuccess && overlap) e = hipEventRecord(ev[3 + b], st);
     if (e == hipSuccess) e = begin_mark(st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-    e = fzp::launch_col_pass(ih.dev, r0, r1, T, split, chunks[i].nseg, seg_stride, roi, st);
+    if (split)
+      e = fzp::launch_col_pass_split(ih.dev, r0, r1, (const float2 *)T, chunks[i].nseg, seg_stride,
+                                     (uint16_t *)(ws + p.off_Tb[lane]), (float *)(ws + p.off_C[lane]), roi, st);
+    else
+      e = fzp::launch_col_pass(ih.dev, r0, r1, T, false, chunks[i].nseg, seg_stride, roi, st);
     if (e == hipSuccess) e = end_mark(1, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
   }
