@@ -190,6 +190,33 @@ def test_split_creases_ragged(N, M, chunk):
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("M,creased", [(272, False), (512, True)])
+def test_split_ranges_at_odd_rows_add_up(M, creased):
+    """Row ranges that start and end inside the 16- and 32-row blocks of the
+    column GEMM's K operand (rows outside a range are masked to zero there)
+    add up to the whole aperture; ROI row tiles past M are ragged."""
+    N = 2048
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N)
+    inst = dict(lam=LAM0, M=M)
+    if creased:
+        inst["creases"] = crease_draws(5, 2e-3, LAM0, 8)
+    announce(f"split ranges at odd rows M={M} creased={creased}")
+    plan = P.Plan(ap, [inst], path="split")
+    ws, roi = plan.alloc()
+    cuts = [0, 37, 1000, 1001, 1013, 1531, N]
+    for k in range(len(cuts) - 1):
+        plan.propagate_range(ws, roi, cuts[k], cuts[k + 1], accumulate=k > 0)
+    torch.cuda.synchronize()
+    U = plan.roi_view(roi, 0).cpu().numpy()
+    _, _, _, (Uw,) = run_gpu(ap, [inst], path="split")
+    a, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    e = rel_l2(O.intensity(U), O.intensity(ref))
+    announce(f"  ranges vs oracle intensity rel-L2 {e:.3e}, vs one call {rel_l2(U, Uw):.3e}")
+    assert e <= 1e-4
+    assert rel_l2(U, Uw) <= 1e-4
+
+
 def test_split_mixed_instances():
     """One plan, one workspace: a flat and a creased instance at two wavelengths,
     sharing the operand table (lambda z is fixed at the first-order focus)."""
