@@ -266,55 +266,13 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_row_pass_fp64(InstDev d, int
   }
 }
 
-__device__ __forceinline__ double2 to_c64(double2 v) { return v; }
-__device__ __forceinline__ double2 to_c64(float2 v) { return make_double2((double)v.x, (double)v.y); }
-
-// Split-path column input: the float32 partial planes of one ROI column
-// (real column 2q, imaginary column 2q + 1 = rs floats further), nseg planes
-// `plane` floats apart, summed in float64 in plane order.  Each plane's 32
-// loads of a block are issued before any is used.
-struct SplitColumn {
-  static constexpr bool kBlock = true;
-  const float *re;  // plane 0, real column, row row_begin
-  int64_t rs;
-  int64_t plane;
-  int nseg;
-  int64_t row_begin;
-  __device__ __forceinline__ void block(int64_t i0, int64_t cnt, double2 v[16]) const {
-    const int t = threadIdx.x;
-    const float *src = re + (i0 - row_begin);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = make_double2(0.0, 0.0);
-    for (int sgi = 0; sgi < nseg; ++sgi) {
-      const float *p = src + (int64_t)sgi * plane;
-      float a[16], b[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int n = t + 256 * r;
-        const int k = n < cnt ? n : 0;  // lanes past the block re-read row i0
-        a[r] = p[k];
-        b[r] = p[rs + k];
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if (t + 256 * r < cnt) {
-          v[r].x += (double)a[r];
-          v[r].y += (double)b[r];
-        }
-      }
-    }
-  }
-};
-
-// Column pass: one work-group per ROI column q (grid-stride).  Adds
+// Column pass of the FP64 path: one work-group per ROI column q (grid-stride)
+// over the chunk's T[j][q] (complex float64, row-major).  Adds
 // F[p,q] Qy[p] sum_blocks(...) into roi[p][q]; each ROI element is owned by one
 // work-group, so the float64 sum over chunks is a fixed-order sequence.
-// FP64 path: T[j][q] complex float64, row-major.  Split path: nseg float32
-// partial planes (K segments), seg_stride complex elements apart, each stored
-// column-major per real column; they are summed here in float64.
-template <int NQ, typename TT>
+template <int NQ>
 __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t row_begin, int64_t row_end,
-                                                             const TT *__restrict__ T, int nseg, int64_t seg_stride,
+                                                             const double2 *__restrict__ T,
                                                              double2 *__restrict__ roi) {
   __shared__ double2 s_lds[kLdsN];
   const int t = threadIdx.x;
@@ -327,16 +285,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   if (gridDim.x == (unsigned)M && (M & 7) == 0) q0 = (q0 & 7) * (M >> 3) + (q0 >> 3);
   for (int q = q0; q < M; q += gridDim.x) {
     double2 acc[NQ];
-    if constexpr (sizeof(TT) == sizeof(float2)) {
-      // split path: float32 partial planes, column-major per real column
-      // (re = column 2q, im = column 2q + 1, row stride rs = chunk rows)
-      const int64_t rs = seg_stride / M;
-      const SplitColumn col{(const float *)T + (int64_t)(2 * q) * rs, rs, 2 * seg_stride, nseg, row_begin};
-      bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc, col);
-    } else {
-      bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc,
-                         [&](int64_t j) -> double2 { return to_c64(T[(j - row_begin) * (int64_t)M + q]); });
-    }
+    bluestein_line<NQ>(d, d.Hy, d.sy, row_begin, row_end, s_lds, tw, acc,
+                       [&](int64_t j) -> double2 { return T[(j - row_begin) * (int64_t)M + q]; });
     const double xq = d.x0 + ((double)q - 0.5 * (double)M) * d.dx_out;
 #pragma unroll
     for (int r = 0; r < NQ; ++r) {
@@ -403,17 +353,12 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
   return hipGetLastError();
 }
 
-hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T, bool t_is_fp32,
-                           int nseg, int64_t seg_stride, double2 *roi, hipStream_t st) {
+hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,
+                           hipStream_t st) {
   if (row_end <= row_begin) return hipSuccess;
   const int grid = d.M;
-#define FZP_COL(NQ)                                                                                         \
-  if (t_is_fp32)                                                                                            \
-    hipLaunchKernelGGL((k_col_pass<NQ, float2>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, \
-                       (const float2 *)T, nseg, seg_stride, roi);                                           \
-  else                                                                                                      \
-    hipLaunchKernelGGL((k_col_pass<NQ, double2>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, \
-                       (const double2 *)T, 1, (int64_t)0, roi);
+#define FZP_COL(NQ) \
+  hipLaunchKernelGGL((k_col_pass<NQ>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, T, roi);
   if (d.M <= 256) {
     FZP_COL(1)
   } else if (d.M <= 512) {

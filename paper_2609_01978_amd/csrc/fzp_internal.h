@@ -138,8 +138,8 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
                                       int64_t seg_stride, const uint16_t *G, hipStream_t st);
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
                                  float2 *T, int64_t seg_stride, const uint32_t *bits, hipStream_t st);
-hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const void *T,
-                           bool t_is_fp32, int nseg, int64_t seg_stride, double2 *roi, hipStream_t st);
+hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,
+                           hipStream_t st);  // FP64 path
 // Split path column pass as a split-BF16 GEMM (fzp_cplx.hip): the column kernel
 // matrix B_y (col_table_bytes, built once per workspace), the chunk's T as a
 // BF16 hi/lo operand (col_operand_bytes per lane) and float32 partial planes

@@ -633,7 +633,7 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
       e = fzp::launch_col_pass_split(ih.dev, r0, r1, (const float2 *)T, chunks[i].nseg, seg_stride,
                                      (uint16_t *)(ws + p.off_Tb[lane]), (float *)(ws + p.off_C[lane]), roi, st);
     else
-      e = fzp::launch_col_pass(ih.dev, r0, r1, T, false, chunks[i].nseg, seg_stride, roi, st);
+      e = fzp::launch_col_pass(ih.dev, r0, r1, (const double2 *)T, roi, st);
     if (e == hipSuccess) e = end_mark(1, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: column pass", e);
   }
