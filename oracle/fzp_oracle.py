@@ -1,5 +1,6 @@
 """FP64 CPU oracle for the stripe-processed chirp-z Fresnel propagation of a
-binary-amplitude Fresnel zone plate (FZP) onto a focal-plane region of interest.
+binary-amplitude (or L-level phase) Fresnel zone plate (FZP) onto a focal-plane
+region of interest.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import or call this module.  The GPU
@@ -35,6 +36,11 @@ reasons, in the design notes of the repository):
   the disc ``K <= K_max`` and ``n`` is odd (``centre_open`` flips the parity);
   ``K_max = N^2`` for the default pitch ``D/N`` and ``floor((D/pitch)^2)``
   otherwise;
+* an L-level phase plate (the revised engine's element, Fig. 18 stage 3)
+  transmits ``exp(-2 pi i l / L)`` on the whole disc with the level
+  ``l = floor(K * kappa_L) mod L``, ``kappa_L = kappa * (L/2)``: the ideal lens
+  phase ``-pi r^2/(lambda0 f0)`` quantised into L equal steps per period of two
+  zones (``L = 2`` gives +1 / -1 on even / odd zones);
 * each instance is evaluated at its first-order focus ``z = f0 lambda0 / lambda``
   unless ``z`` is given;
 * a membrane deformation is a thin phase screen ``phi = 2 pi h / lambda`` of
@@ -62,7 +68,7 @@ from scipy.interpolate import CubicSpline
 
 __all__ = [
     "Aperture", "Instance", "resolve", "aperture_coords", "roi_coords",
-    "zone_mask", "incident_count", "crease_height", "aperture_field",
+    "zone_mask", "disc_mask", "phase_level", "incident_count", "crease_height", "aperture_field",
     "fresnel_direct", "czt_direct", "czt_bluestein", "propagate",
     "output_factor", "intensity", "metrics", "fwhm_1d", "mtf_half_cut",
     "hankel_field", "hankel_intensity", "hankel_metrics", "on_axis_closed_form",
@@ -87,13 +93,16 @@ AIRY_LOBE_FRACTION = 1.0 - special.j0(J11) ** 2 - special.j1(J11) ** 2
 
 @dataclass
 class Aperture:
-    """A binary-amplitude FZP sampled on an N x N grid (Sec. 2.2, Sec. 3.3)."""
+    """An FZP sampled on an N x N grid (Sec. 2.2, Sec. 3.3): binary amplitude
+    (levels = 0), or an L-level phase plate (levels = L >= 2, the revised
+    engine's element, Fig. 18 stage 3 and Tables 1-5)."""
     D: float                 # aperture diameter [m]
     f0: float                # design focal length [m]
     lambda0: float           # design wavelength [m]
     N: int                   # samples per side
     pitch: float = 0.0       # sample pitch [m]; 0 means D / N
-    centre_open: int = 0     # 0: zone 0 (the centre) opaque; 1: centre open
+    centre_open: int = 0     # 0: zone 0 (the centre) opaque; 1: centre open (amplitude plates)
+    levels: int = 0          # 0: binary amplitude; L >= 2: L-level phase
 
     @property
     def dx(self) -> float:
@@ -157,6 +166,36 @@ def zone_mask(ap: Aperture, j0: int = 0, j1: Optional[int] = None) -> np.ndarray
     return (K <= ap.k_max) & odd
 
 
+def disc_mask(ap: Aperture, j0: int = 0, j1: Optional[int] = None) -> np.ndarray:
+    """Samples of rows j0..j1-1 inside the aperture disc K <= K_max (bool)."""
+    j1 = ap.N if j1 is None else j1
+    N = ap.N
+    ci = 2 * np.arange(N, dtype=np.int64) - (N - 1)
+    cj = 2 * np.arange(j0, j1, dtype=np.int64) - (N - 1)
+    return cj[:, None] ** 2 + ci[None, :] ** 2 <= ap.k_max
+
+
+def phase_level(ap: Aperture, j0: int = 0, j1: Optional[int] = None) -> np.ndarray:
+    """Phase level l in 0..L-1 of an L-level phase plate on rows j0..j1-1.
+
+    With s = r^2 / (lambda0 f0) (the zone coordinate of Eq. 4; zone n covers
+    n <= s < n + 1), the ideal lens phase -pi s is quantised per period of two
+    zones into L equal steps (Fig. 18 stage 3): l = floor(L frac(s / 2)), i.e.
+    l = floor(K kappa_L) mod L with kappa_L = kappa * (L/2), one float64 product
+    like the zone rule (for L = 2, l is the zone parity).  The transmission is
+    exp(-2 pi i l / L) inside the disc.
+    """
+    j1 = ap.N if j1 is None else j1
+    L = int(ap.levels)
+    N = ap.N
+    ci = 2 * np.arange(N, dtype=np.int64) - (N - 1)
+    cj = 2 * np.arange(j0, j1, dtype=np.int64) - (N - 1)
+    K = cj[:, None] ** 2 + ci[None, :] ** 2
+    kappa = ap.dx * ap.dx / (4.0 * ap.lambda0 * ap.f0)
+    kappa_l = kappa * (0.5 * L)
+    return np.floor(K.astype(np.float64) * kappa_l).astype(np.int64) % L
+
+
 def incident_count(ap: Aperture) -> int:
     """Number of samples inside the aperture disc K <= K_max (exact integers).
 
@@ -198,7 +237,11 @@ def crease_height(x: np.ndarray, y: np.ndarray, creases: Optional[np.ndarray]) -
 def aperture_field(ap: Aperture, inst: Instance, j0: int = 0, j1: Optional[int] = None) -> np.ndarray:
     """Aperture transmittance t * exp(i phi) on rows j0..j1-1 (complex, rows x N)."""
     j1 = ap.N if j1 is None else j1
-    t = zone_mask(ap, j0, j1).astype(np.complex128)
+    if ap.levels >= 2:
+        L = int(ap.levels)
+        t = np.where(disc_mask(ap, j0, j1), np.exp(-2j * np.pi * phase_level(ap, j0, j1) / L), 0.0)
+    else:
+        t = zone_mask(ap, j0, j1).astype(np.complex128)
     if inst.creases is not None and len(inst.creases):
         x = aperture_coords(ap)
         y = x[j0:j1]
@@ -427,16 +470,28 @@ def metrics(U_or_I: np.ndarray, ap: Aperture, inst: Instance, p_in_count: Option
 # ----------------------------------------------------------------------------
 
 def _open_zone_intervals(ap: Aperture, s_max: float):
-    """Open zones in s = r^2: [n lambda0 f0, (n+1) lambda0 f0] for odd n (even n
-    when the centre is open), clipped at s_max."""
+    """Intervals of s = r^2 with constant transmission, clipped at s_max, and
+    that transmission.  Amplitude plate: the open zones
+    [n lambda0 f0, (n+1) lambda0 f0] for odd n (even n when the centre is open),
+    transmission 1.  L-level phase plate: the steps
+    [m, m+1] * 2 lambda0 f0 / L, transmission exp(-2 pi i (m mod L) / L)."""
     a = ap.lambda0 * ap.f0
+    if ap.levels >= 2:
+        L = int(ap.levels)
+        step = 2.0 * a / L
+        nz = int(np.ceil(s_max / step)) + 1
+        m = np.arange(nz)
+        lo = m * step
+        hi = np.minimum((m + 1) * step, s_max)
+        ok = lo < hi
+        return lo[ok], hi[ok], np.exp(-2j * np.pi * (m[ok] % L) / L)
     nz = int(np.ceil(s_max / a)) + 1
     n = np.arange(nz)
     keep = (n % 2 == 1) if not ap.centre_open else (n % 2 == 0)
     lo = n[keep] * a
     hi = np.minimum((n[keep] + 1) * a, s_max)
     ok = lo < hi
-    return lo[ok], hi[ok]
+    return lo[ok], hi[ok], np.ones(int(ok.sum()), dtype=np.complex128)
 
 
 def hankel_field(rho: np.ndarray, ap: Aperture, lam: float, z: float, nodes: int = 16) -> np.ndarray:
@@ -446,11 +501,11 @@ def hankel_field(rho: np.ndarray, ap: Aperture, lam: float, z: float, nodes: int
     the same units as |U|^2 from ``propagate``.  Gauss-Legendre per open zone.
     """
     lz = lam * z
-    lo, hi = _open_zone_intervals(ap, (0.5 * ap.D) ** 2)
+    lo, hi, tz = _open_zone_intervals(ap, (0.5 * ap.D) ** 2)
     t, wts = np.polynomial.legendre.leggauss(nodes)
     half = 0.5 * (hi - lo)
     s = (0.5 * (hi + lo))[:, None] + half[:, None] * t[None, :]
-    wt = (half[:, None] * wts[None, :]).ravel()
+    wt = (tz[:, None] * half[:, None] * wts[None, :]).ravel()
     s = s.ravel()
     ph = np.exp(1j * np.pi * s / lz) * wt
     rho = np.atleast_1d(np.asarray(rho, dtype=np.float64))
@@ -496,8 +551,8 @@ def on_axis_closed_form(ap: Aperture, lam: Optional[float] = None, z: Optional[f
     lam = ap.lambda0 if lam is None else lam
     z = ap.f0 * ap.lambda0 / lam if z is None else z
     lz = lam * z
-    lo, hi = _open_zone_intervals(ap, (0.5 * ap.D) ** 2)
-    s = np.sum(np.exp(1j * np.pi * hi / lz) - np.exp(1j * np.pi * lo / lz))
+    lo, hi, tz = _open_zone_intervals(ap, (0.5 * ap.D) ** 2)
+    s = np.sum(tz * (np.exp(1j * np.pi * hi / lz) - np.exp(1j * np.pi * lo / lz)))
     return float(abs(s) ** 2)
 
 

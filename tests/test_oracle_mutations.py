@@ -14,6 +14,7 @@ import pytest
 
 from oracle import fzp_oracle as O
 import test_oracle_pins as pins
+import test_oracle_multilevel_pins as mpins
 
 ORIG = {name: getattr(O, name) for name in dir(O) if callable(getattr(O, name))}
 
@@ -43,6 +44,10 @@ def _pins():
         ("hankel_airy", pins.test_hankel_tends_to_airy_at_many_zones),
         ("airy_consts", pins.test_airy_constants_against_paper),
         ("eq3", pins.test_zone_count_eq3),
+        ("ml_levels", lambda: mpins.test_phase_level_exact_rationals(4, 63)),
+        ("ml_two", mpins.test_two_levels_is_open_minus_closed_amplitude_plate),
+        ("ml_ladder", lambda: mpins.test_efficiency_ladder_at_many_zones(4)),
+        ("ml_axis", mpins.test_small_grid_on_axis_matches_hankel),
     ]
 
 
@@ -170,6 +175,22 @@ def m_eq3_paraxial(D, lam, f):
     return (0.5 * D) ** 2 / (lam * f)
 
 
+def m_level_kappa_full_l(ap, j0=0, j1=None):
+    j1 = ap.N if j1 is None else j1
+    a = O.Aperture(D=ap.D, f0=ap.f0, lambda0=ap.lambda0, N=ap.N, pitch=ap.pitch, levels=2 * ap.levels)
+    return ORIG["phase_level"](a, j0, j1) % ap.levels      # kappa * L instead of kappa * L/2
+
+
+def m_field_phase_sign(ap, inst, j0=0, j1=None):
+    return np.conj(ORIG["aperture_field"](ap, inst, j0, j1)) if ap.levels >= 2 else \
+        ORIG["aperture_field"](ap, inst, j0, j1)
+
+
+def m_intervals_phase_sign(ap, s_max):
+    lo, hi, t = ORIG["_open_zone_intervals"](ap, s_max)
+    return lo, hi, np.conj(t)
+
+
 MUTANTS = {
     "czt_bluestein": m_bluestein_post_chirp_sign,
     "czt_direct": m_czt_direct_a_sign,
@@ -193,6 +214,9 @@ MUTANTS = {
     "on_axis_closed_form": m_closed_form_centre_open,
     "incident_count": m_incident_off_by_one,
     "zone_count_exact": m_eq3_paraxial,
+    "phase_level/kappa": m_level_kappa_full_l,
+    "aperture_field/phase_sign": m_field_phase_sign,
+    "_open_zone_intervals/phase_sign": m_intervals_phase_sign,
 }
 
 
