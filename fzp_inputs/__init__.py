@@ -15,6 +15,9 @@ element in its accuracy study, Sec. 4.1, and its meter-class runs, Tables 1-5):
 * ``batch64``  64 instances of the D=20 mm element: 16 wavelengths (500-800 nm)
                x 4 crease maps, ROI sizes drawn from {256, 512, 1024}
 * ``surrogate`` D=10 mm, f=50 mm, N=16384, M=128, 8 random creases + lambda
+* ``ml100mm``  D=0.1 m, f=0.5 m (f/5), lambda0=632.8 nm, a 4-level phase plate,
+               N=2^18 (0.38 um pitch, finer than the revised engine's grid rule
+               Lambda_edge / (4 max(L, 2)) = 0.40 um), M=512, stripe 128
 
 The crease model (a thin phase screen of straight Gaussian ridges) is a reading
 of the membrane deformations that the introduction names as the motivation for
@@ -46,6 +49,7 @@ WORKLOADS = {
     "surrogate": dict(D=10e-3, f0=50e-3, lambda0=LAMBDA0, N=16384, M=128, stripe=128,
                       n_creases=8, lambda_lo=500e-9, lambda_hi=800e-9,
                       n_train=20000, n_test=1000, train_seed=10, test_seed=11),
+    "ml100mm": dict(D=0.1, f0=0.5, lambda0=LAMBDA0, N=1 << 18, M=512, stripe=128, levels=4),
 }
 
 

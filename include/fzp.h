@@ -89,8 +89,13 @@ typedef struct {
   double lambda0;    /* design wavelength (zone radii r_n^2 = n lambda0 f0) */
   double pitch;      /* sample pitch; 0 means D / N */
   int64_t N;         /* samples per side, 1 .. 2^21 */
-  int32_t centre_open; /* 0: central zone opaque (odd zones open); 1: central zone open */
-  int32_t reserved;
+  int32_t centre_open; /* amplitude plates: 0 central zone opaque (odd zones open), 1 central
+                          zone open; must be 0 for phase plates */
+  int32_t levels;      /* 0: binary amplitude plate (Sec. 2.2).  2 .. 64: L-level phase plate
+                          (the revised engine's element, Fig. 18 stage 3): on the whole disc
+                          the transmission is exp(-2 pi i l / L), l = floor(K kappa_L) mod L,
+                          kappa_L = kappa * (L / 2), kappa = pitch^2 / (4 lambda0 f0), the ideal
+                          lens phase -pi r^2 / (lambda0 f0) quantised into L steps per period */
 } fzp_aperture_t;
 
 typedef struct {

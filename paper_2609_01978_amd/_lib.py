@@ -56,7 +56,7 @@ class FZPError(RuntimeError):
 class Aperture(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("f0", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("pitch", ctypes.c_double), ("N", ctypes.c_int64), ("centre_open", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("levels", ctypes.c_int32)]
 
 
 class Crease(ctypes.Structure):
@@ -187,7 +187,8 @@ class Plan:
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
                       pitch=aperture.get("pitch", 0.0), N=int(aperture["N"]),
-                      centre_open=int(aperture.get("centre_open", 0)), reserved=0)
+                      centre_open=int(aperture.get("centre_open", 0)),
+                      levels=int(aperture.get("levels", 0)))
         n = len(instances)
         arr = (Instance * n)()
         self._crease_bufs = []

@@ -114,15 +114,33 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     const int64_t i0 = 16 * (kb0 + kb);
     if (i0 < t_lo || i0 >= t_hi) continue;
     const double c0 = (double)(2 * i0 - N + 1);
-    // zone mask of the 16 samples (exact integer rule)
+    // zone mask of the 16 samples (exact integer rule); for an L-level phase
+    // plate every disc sample passes and carries -l/L turns of lens phase,
+    // l = floor(K kappa_L) mod L
     uint32_t open = 0;
+    float turns[16];
+    if (d.levels != 0) {
+      const int L = d.levels;
+      const float inv_l = 1.0f / (float)L;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const double ci = c0 + 2.0 * e;
-      const double K = fma(ci, ci, bj);
-      const int zone = (int)(K * d.kappa);
-      const bool o = live && i0 + e < N && K <= d.kmax && (((zone & 1) ^ d.centre_open) != 0);
-      open |= (o ? 1u : 0u) << e;
+      for (int e = 0; e < 16; ++e) {
+        const double ci = c0 + 2.0 * e;
+        const double K = fma(ci, ci, bj);
+        const int lv = (int)(K * d.kappa_l) % L;
+        const bool o = live && i0 + e < N && K <= d.kmax;
+        open |= (o ? 1u : 0u) << e;
+        turns[e] = -(float)lv * inv_l;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double ci = c0 + 2.0 * e;
+        const double K = fma(ci, ci, bj);
+        const int zone = (int)(K * d.kappa);
+        const bool o = live && i0 + e < N && K <= d.kmax && (((zone & 1) ^ d.centre_open) != 0);
+        open |= (o ? 1u : 0u) << e;
+        turns[e] = 0.0f;
+      }
     }
     // Crease phase in turns.  Along the row the ridge distance d grows by
     // st = dx cos(theta) per sample, so the Gaussian g = exp(-a d^2) obeys
@@ -132,9 +150,6 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     // below 2^-30 turns over all 16 samples (|h| exp(-a d^2) < 2^-30 at the
     // nearest of them) is skipped; neighbouring rows of a wave see nearly the
     // same distances, so the skip is close to wave-uniform.
-    float turns[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) turns[e] = 0.0f;
     const double x0 = hdx * c0;
     for (int k = 0; k < nc; ++k) {
       const float dd = (float)fma(x0, cr[k].c, fma(y, cr[k].s, -cr[k].rho));

@@ -197,16 +197,29 @@ struct CreasedRow {
     const double c0 = (double)(2 * (i0 + t) - N + 1);
     const double x0 = 0.5 * c0 * d->dx;
     bool open[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const double ci = c0 + 512.0 * r;
-      const double K = ci * ci + bj;  // exact integer
-      const int zone = (int)(K * d->kappa);
-      open[r] = t + 256 * r < cnt && ((zone & 1) ^ d->centre_open) != 0;
-    }
     double turns[16];
+    if (d->levels != 0) {
+      // L-level phase plate: every disc sample passes, with the lens phase
+      // quantised to level l = floor(K kappa_L) mod L, -l/L turns
+      const int L = d->levels;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) turns[r] = 0.0;
+      for (int r = 0; r < 16; ++r) {
+        const double ci = c0 + 512.0 * r;
+        const double K = ci * ci + bj;  // exact integer
+        const int lv = (int)(K * d->kappa_l) % L;
+        open[r] = t + 256 * r < cnt;
+        turns[r] = -(double)lv / (double)L;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const double ci = c0 + 512.0 * r;
+        const double K = ci * ci + bj;  // exact integer
+        const int zone = (int)(K * d->kappa);
+        open[r] = t + 256 * r < cnt && ((zone & 1) ^ d->centre_open) != 0;
+        turns[r] = 0.0;
+      }
+    }
     for (int k = 0; k < d->n_creases; ++k) {
       const CreaseDev &cr = d->cr[k];
       const double a = cr.inv2s2, h = cr.h_over_lambda;
@@ -334,7 +347,7 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
   const int grid = grid_for(rows, 2);
-  const bool def = d.n_creases > 0;
+  const bool def = d.n_creases > 0 || d.levels != 0;  // complex aperture samples
 #define FZP_ROW(NQ)                                                                                          \
   if (def)                                                                                                   \
     hipLaunchKernelGGL((k_row_pass_fp64<NQ, true>), dim3(grid), dim3(kFftThreads), 0, st, d, row_begin, row_end, T); \

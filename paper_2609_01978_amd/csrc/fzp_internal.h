@@ -58,7 +58,8 @@ struct InstDev {
   int32_t bin_tile_rows;   // split path, binary stripes: GEMM tile rows (512 or 256)
   int32_t bin_ring;        // split path, binary stripes, 512-row tile: LDS pipeline stages (4 or 8)
   int32_t bin_prefetch;    // 8-stage variant: 1 next-stage operands one stage early, 2 interleaved expansion
-  int32_t pad_;
+  int32_t levels;          // 0: binary amplitude plate; L >= 2: L-level phase plate
+  double kappa_l;          // phase plates: kappa * (L / 2); level = floor(K kappa_l) mod L
 };
 
 struct InstHost {

@@ -120,6 +120,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     if (!(std::isfinite(ap->pitch) && ap->pitch >= 0.0)) return fail(FZP_E_INVAL, "fzp_plan: pitch must be >= 0");
     if (ap->N < 1 || ap->N > (int64_t(1) << 21)) return fail(FZP_E_INVAL, "fzp_plan: N must be in 1 .. 2^21");
     if (ap->centre_open != 0 && ap->centre_open != 1) return fail(FZP_E_INVAL, "fzp_plan: centre_open must be 0 or 1");
+    if (ap->levels != 0 && (ap->levels < 2 || ap->levels > 64))
+      return fail(FZP_E_INVAL, "fzp_plan: levels must be 0 (amplitude plate) or 2 .. 64 (phase plate)");
+    if (ap->levels != 0 && ap->centre_open != 0)
+      return fail(FZP_E_INVAL, "fzp_plan: centre_open applies to amplitude plates only");
     if (o.stripe_rows < 0 || o.chunk_rows < 0) return fail(FZP_E_INVAL, "fzp_plan: negative stripe or chunk rows");
     if (o.lanes < 0 || o.lanes > 8) return fail(FZP_E_INVAL, "fzp_plan: lanes must be in 0 .. 8");
 
@@ -147,9 +151,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       delete h;
       return fail(FZP_E_SAMPLING, "fzp_plan: pitch exceeds the Nyquist limit lambda0 f0 / (2 D) of Eq. 6");
     }
-    // zone indices must fit int32 over the whole square grid
+    // zone (or phase-step) indices must fit int32 over the whole square grid
     const double kcorner = 2.0 * (double)(N - 1) * (double)(N - 1);
-    if (!(kcorner * p.kappa < 2.0e9)) {
+    const double step_scale = ap->levels != 0 ? 0.5 * (double)ap->levels : 1.0;
+    if (!(kcorner * p.kappa * step_scale < 2.0e9)) {
       delete h;
       return fail(FZP_E_UNSUPPORTED, "fzp_plan: zone count beyond 2e9");
     }
@@ -193,6 +198,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       d.kappa = p.kappa;
       d.kmax = (double)p.kmax;
       d.centre_open = ap->centre_open;
+      d.levels = ap->levels;
+      d.kappa_l = p.kappa * (0.5 * (double)ap->levels);
       d.M = in.M;
       d.B = fzp::kFftLen - in.M + 1;
       d.n_creases = in.n_creases;
@@ -227,9 +234,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       delete h;
       return fail(FZP_E_INVAL, "fzp_plan: split path stripe_rows must be 64, 128 or 256");
     }
-    bool cplx = false;  // split path with deformed (complex) stripes
+    bool cplx = false;  // split path with complex stripes (creases or a phase plate)
     if (split)
-      for (const auto &ih : p.inst) cplx = cplx || ih.in.n_creases > 0;
+      for (const auto &ih : p.inst) cplx = cplx || ih.in.n_creases > 0 || ap->levels != 0;
     if (split)
       for (const auto &ih : p.inst)
         if (ih.in.M % 16 != 0) {
@@ -531,7 +538,7 @@ hipError_t ensure_aux(Plan &p) {
 fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2 *roi, int64_t row_begin,
                               int64_t row_end, hipStream_t st) {
   const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
-  const bool cplx = split && ih.dev.n_creases > 0;
+  const bool cplx = split && (ih.dev.n_creases > 0 || ih.dev.levels != 0);
   void *T = ws + p.off_T[lane];
   hipError_t e;
   // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples
@@ -860,6 +867,7 @@ std::string tune_key(const Plan &p) {
     if (c == ' ' || c == ':') c = '_';
   k << "fzp1/" << arch << "/N" << p.ap.N << "/path" << p.opt.path << "/chunk" << p.chunk_rows << "/L"
     << p.lanes_max;
+  if (p.ap.levels != 0) k << "/phase" << p.ap.levels;
   // the multiset of (M, deformed) over instances, in instance order
   for (const auto &ih : p.inst) k << "/" << ih.dev.M << (ih.dev.n_creases > 0 ? "c" : "f");
   return k.str();
