@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch of the 20 mm element")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
+    ap.add_argument("--no-multilevel", action="store_true", help="skip the 0.1 m 4-level phase plate")
+    ap.add_argument("--multilevel-steps", type=int, default=2)
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and evaluate the learned surrogate (20k + 1k CZT solves)")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
@@ -162,6 +164,53 @@ def run_batch(args, dev):
             "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
             "max_rel_l2_split_vs_fp64": max(errs), "valid_rel_l2_le_1e-4": max(errs) <= 1e-4,
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_batch"] / res["split"]["ms_per_batch"], 3)}
+
+
+def run_multilevel(args, dev):
+    """The 0.1 m f/5 4-level phase plate (the revised engine's kind of element)
+    on both paths: one propagation plus metrics per step.  Valid when the split
+    intensity is within rel-L2 1e-4 of the FP64 path's; the main-lobe DE is
+    reported next to the L-level ladder value sinc^2(1/L) times the Airy lobe
+    share 1 - J0(j_{1,1})^2."""
+    import math
+    import numpy as np
+    import torch
+    from scipy import special
+    import paper_2609_01978_amd as P
+    from fzp_inputs import workload
+    w = workload("ml100mm")
+    L = w["levels"]
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"], levels=L)
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    samples = float(w["N"]) ** 2
+    res, I = {}, {}
+    for path in ("split", "fp64"):
+        plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"] if path == "split" else 0)
+        ws, roi = plan.alloc(dev)
+        plan.prepare(ws)
+        plan.propagate(ws, roi)
+        plan.metrics(ws, roi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.multilevel_steps):
+            plan.propagate(ws, roi)
+            m = plan.metrics(ws, roi)[0]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.multilevel_steps
+        log(f"ml100mm {path}: {dt * 1e3:.1f} ms per propagation")
+        I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
+        res[path] = {"gsamples_s": round(samples / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
+                     "de": m["de"], "fwhm_x": m["fwhm_x"], "strehl": m["strehl"]}
+        del ws, roi, plan
+        torch.cuda.empty_cache()
+    e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
+    x = math.pi / L
+    lobe = 1.0 - float(special.j0(special.jn_zeros(1, 1)[0])) ** 2
+    return {"workload": f"{L}-level phase FZP D={w['D']} m f/5 lambda0=632.8 nm, N={w['N']}^2, ROI {w['M']}^2",
+            "steps": args.multilevel_steps, "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
+            "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
+            "de_ladder_sinc2": round((math.sin(x) / x) ** 2 * lobe, 6),
+            "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
 
 
 def main():
@@ -311,6 +360,8 @@ def main():
         out["speedup_split_vs_fp64"] = round(fp64["ms"] / split["ms"], 3)
     if not args.no_batch:
         out["batch64"] = run_batch(args, dev)
+    if not args.no_multilevel:
+        out["ml100mm"] = run_multilevel(args, dev)
     if args.surrogate:
         from paper_2609_01978_amd import surrogate as SG
         sw = workload("surrogate")

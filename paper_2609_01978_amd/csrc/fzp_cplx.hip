@@ -18,8 +18,19 @@ constexpr int kCThreads = 512;
 // work-group barrier makes them visible.  One asm statement, so that the
 // compiler does not put a wait for all outstanding copies in front of the
 // barrier.
-__device__ __forceinline__ void stage_barrier() {
-  asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+// Wait until at most N of this wave's copies are in flight (the newest
+// stage's), then barrier: N = 6 with all four stripe planes, 4 with the hi
+// planes only.
+template <int N> __device__ __forceinline__ void stage_barrier() {
+  static_assert(N == 4 || N == 6, "add the count");
+  if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// A 2- or 4-level phase plate without creases has stripe values 0, +-1, +-i:
+// exact in BF16, so its lo planes are zero and are neither written nor read.
+__host__ __device__ __forceinline__ bool stripe_exact(const InstDev &d) {
+  return (d.levels == 2 || d.levels == 4) && d.n_creases == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -85,6 +96,9 @@ __device__ __forceinline__ void sincos_turns(float t, float &sn, float &cs) {
 // instruction; the same result as the integer rounding of the operand table).
 __device__ __forceinline__ uint16_t bf16_cvt(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
+// PHASE: an L-level phase plate (levels != 0); EXACT: its values are exact in
+// BF16 (stripe_exact), so only the hi planes are written.
+template <bool PHASE, bool EXACT>
 __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
                                                      int64_t rows_pad, int64_t kb0, int64_t nkb,
                                                      uint16_t *__restrict__ G) {
@@ -119,7 +133,7 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     // l = floor(K kappa_L) mod L
     uint32_t open = 0;
     float turns[16];
-    if (d.levels != 0) {
+    if constexpr (PHASE) {
       const int L = d.levels;
       const float inv_l = 1.0f / (float)L;
 #pragma unroll
@@ -192,6 +206,7 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      if ((v & 1) && EXACT) continue;
       u32x4 *dst = (u32x4 *)(G + v * plane + (kb * rows_pad + rl) * 16);
       dst[0] = u32x4{w[v][0], w[v][1], w[v][2], w[v][3]};
       dst[1] = u32x4{w[v][4], w[v][5], w[v][6], w[v][7]};
@@ -213,11 +228,15 @@ __device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
 // chord).  With COL the same kernel is the column pass of the split path:
 // rows are ROI rows p, K is the chunk's aperture rows j (segments of
 // seg_len_c rows, no chord), the A operand the column kernel matrix B_y and
-// the B operand the chunk's row-pass result T (see k_col_operand).  8 waves in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4
-// MFMA 32x32 blocks (128 float32 accumulators per lane), 6 MFMAs per block
-// per K-step.  Stripe and table slabs move HBM -> LDS by direct copies into a
+// the B operand the chunk's row-pass result T (see k_col_operand).  8 waves
+// in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4 MFMA 32x32 blocks
+// (128 float32 accumulators per lane), 6 MFMAs per block per K-step (4 when
+// GLO is false).  Stripe and table slabs move HBM -> LDS by direct copies into a
 // 3-deep ring, 2 stages ahead, one barrier per stage.
-template <bool COL>
+// GLO = false: the stripe planes' lo parts are zero (a 2- or 4-level phase
+// plate without creases: every value is 0, +-1 or +-i, exact in BF16), so the
+// g_lo . A_hi products are skipped (4 MFMAs per block per K-step).
+template <bool COL, bool GLO = true>
 __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
     InstDev d, int64_t row_begin, int64_t row_end, int n_rt, int n_ct, int seg_lo, int n_seg,
     const uint16_t *__restrict__ G, int64_t rows_pad, int64_t kb0, int64_t nkb, float *__restrict__ T,
@@ -262,10 +281,16 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   // holds global half chalf(row, L & 1).  Table columns past 2M read column 0:
   // they feed only accumulator columns that are never stored.
   const int64_t plane = nkb * rows_pad * 16;
-  const uint16_t *gsrc[4];
+  // without lo planes (GLO false) each wave copies two pieces of the hi planes
+  // (re_hi = pieces 0-7, im_hi = pieces 16-23)
+  constexpr int NG = GLO ? 4 : 2;
+  const uint16_t *gsrc[NG];
+  int gx[NG];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int x = 4 * wave + j;
+  for (int j = 0; j < NG; ++j) {
+    const int h = 2 * wave + j;
+    const int x = GLO ? 4 * wave + j : (h >> 3) * 16 + (h & 7);
+    gx[j] = x;
     const int row = (x & 7) * 32 + (lane >> 1);
     gsrc[j] = G + (x >> 3) * plane + ((int64_t)rt * kCTR + row) * 16 + 8 * chalf(row, lane & 1);
   }
@@ -305,10 +330,9 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
       char *dst = lds + (s % kCRing) * kCStage;
       const int64_t gofs = (k / 16 - kb0) * rows_pad * 16;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < NG; ++j)
         __builtin_amdgcn_global_load_lds((const void *)(gsrc[j] + gofs),
-                                         (__attribute__((address_space(3))) void *)(dst + (4 * wave + j) * 1024),
-                                         16, 0, 0);
+                                         (__attribute__((address_space(3))) void *)(dst + gx[j] * 1024), 16, 0, 0);
       const int64_t kr = k - kB0;  // K index of the B operand's blocked layout
       const int64_t bofs = (kr >> 5) * M2 * 32 + (kr & 31);
 #pragma unroll
@@ -319,7 +343,7 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
                                          16, 0, 0);
     };
     for (int s = 0; s < kCAhead; ++s) copy_stage(s);
-    asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+    stage_barrier<NG + 2>();
     for (int s = 0; s < nst; ++s) {
       copy_stage(s + kCAhead);
       const char *sb = lds + (s % kCRing) * kCStage;
@@ -335,9 +359,7 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
       for (int rb = 0; rb < 2; ++rb) {
         const char *pa = sb + aoff + rb * 32 * kCRowB;
         const bf16x8 rh = __builtin_bit_cast(bf16x8, lds_ld16(pa));
-        const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
         const bf16x8 ih = __builtin_bit_cast(bf16x8, lds_ld16(pa + 2 * kCTR * kCRowB));
-        const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bh[cb], acc[rb][cb], 0, 0, 0);
@@ -348,13 +370,17 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bls[cb], acc[rb][cb], 0, 0, 0);
         }
+        if constexpr (GLO) {
+          const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
+          const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
-          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
+          for (int cb = 0; cb < 4; ++cb) {
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
+          }
         }
       }
-      stage_barrier();
+      stage_barrier<NG + 2>();
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
@@ -506,6 +532,9 @@ hipError_t init_cplx_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kCLdsBytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<false, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kCLdsBytes);
   return e;
 }
 
@@ -536,7 +565,15 @@ hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_e
   if (gy > nkb) gy = nkb;
   if (gy > 65535) gy = 65535;
   const dim3 grid((unsigned)gx, (unsigned)gy);
-  hipLaunchKernelGGL(k_stripe_cplx, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
+  if (stripe_exact(d))
+    hipLaunchKernelGGL((k_stripe_cplx<true, true>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
+                       nkb, G);
+  else if (d.levels != 0)
+    hipLaunchKernelGGL((k_stripe_cplx<true, false>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
+                       nkb, G);
+  else
+    hipLaunchKernelGGL((k_stripe_cplx<false, false>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
+                       nkb, G);
   return hipGetLastError();
 }
 
@@ -556,9 +593,15 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
   const int64_t grid = (Gn + 255) / 256 * 256;
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
-                     row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride,
-                     d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  // 2- and 4-level phase plates without creases: stripe values exact in BF16
+  if (stripe_exact(d))
+    hipLaunchKernelGGL((k_row_pass_split_cplx<false, false>), dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st,
+                       d, row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
+                       2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  else
+    hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
+                       row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
+                       2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
   return hipGetLastError();
 }
 
