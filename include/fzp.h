@@ -2,7 +2,7 @@
  * fzp.h - C ABI of the MI355X stripe-CZT Fresnel zone plate propagator.
  *
  * The library evaluates the focal-plane field of a full, unscaled, 2-D
- * binary-amplitude Fresnel zone plate (FZP) on a fixed region of interest
+ * binary-amplitude (or L-level phase) Fresnel zone plate (FZP) on a fixed region of interest
  * (ROI), by the separable chirp-z transform of the paper's CZT method
  * (Sec. 2.6, Eqs. 9-10; Sec. 3.3, Fig. 2; revised GPU engine, Sec. 6, Fig. 18):
  *
@@ -16,7 +16,8 @@
  * float64 constant kappa = dx*dx / (4*lambda0*f0), a sample is open iff
  * K <= K_max (inside the aperture disc; K_max = N^2 for the default pitch D/N,
  * floor((D/pitch)^2) otherwise) and floor(K*kappa) is odd (even when
- * centre_open is set).  phi = 2 pi h / lambda is an optional phase screen of
+ * centre_open is set); an L-level phase plate (fzp_aperture_t.levels) instead
+ * passes every disc sample with t = exp(-2 pi i l / L).  phi = 2 pi h / lambda is an optional phase screen of
  * straight Gaussian creases, h = sum_k H_k exp(-d_k^2/(2 sigma_k^2)),
  * d_k = x cos(theta_k) + y sin(theta_k) - rho_k, sigma_k = width_k/(2 sqrt(2 ln 2)).
  * The N x N aperture is never stored: every stripe of rows is generated on the
