@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
     ap.add_argument("--no-multilevel", action="store_true", help="skip the 0.1 m 4-level phase plate")
+    ap.add_argument("--convergence", action="store_true",
+                    help="also run the grid-convergence sweep of the accuracy study (D = 0.08 m, f = 1.5 m, "
+                         "532 nm, N = 1024 .. 28672) on both paths")
     ap.add_argument("--multilevel-steps", type=int, default=2)
     ap.add_argument("--surrogate", action="store_true",
                     help="also train and evaluate the learned surrogate (20k + 1k CZT solves)")
@@ -213,6 +216,58 @@ def run_multilevel(args, dev):
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
 
 
+# Closed forms of the ideal Airy pattern (aberration-free circular pupil):
+# FWHM = 1.028994 lambda f / D (half maximum of (2 J1(v)/v)^2 at v = 1.61634),
+# main-lobe share 1 - J0(j11)^2 of the first order, which carries 1/pi^2 of the
+# incident power for a binary amplitude plate, and the incoherent MTF
+# (2/pi)(acos(s) - s sqrt(1 - s^2)) at s = 1/2.
+AIRY_FWHM_FACTOR = 1.028994
+
+
+def run_convergence(dev):
+    """Grid-convergence sweep of the accuracy study (Sec. 4.1, Figs. 6-8): the
+    binary, negative-centred plate D = 0.08 m, f = 1.5 m at 532 nm on grids
+    N = 1024 .. 28672, ROI 512^2 at +-8 lambda f/#; FWHM, main-lobe DE and MTF
+    at half cutoff against the Airy closed forms, for both paths."""
+    import math
+    import numpy as np
+    import torch
+    from scipy import special
+    import paper_2609_01978_amd as P
+    D, f, lam = 0.08, 1.5, 532e-9
+    j11 = float(special.jn_zeros(1, 1)[0])
+    ref = {"fwhm": AIRY_FWHM_FACTOR * lam * f / D,
+           "de": (1.0 - float(special.j0(j11)) ** 2) / math.pi ** 2,
+           "mtf": 2.0 / math.pi * (math.acos(0.5) - 0.5 * math.sqrt(0.75))}
+    rows = []
+    for N in (1024, 2048, 4096, 8192, 12288, 16384, 20480, 24576, 28672):
+        ap = dict(D=D, f0=f, lambda0=lam, N=N)
+        inst = dict(lam=lam, M=512)
+        I = {}
+        for path in ("split", "fp64"):
+            plan = P.Plan(ap, [inst], path=path, allow_undersampled=True)
+            ws, roi = plan.alloc(dev)
+            plan.prepare(ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.propagate(ws, roi)
+            m = plan.metrics(ws, roi)[0]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
+            rows.append({"N": N, "path": path, "ms": round(dt * 1e3, 3),
+                         "fwhm_err_pct": round(100.0 * (0.5 * (m["fwhm_x"] + m["fwhm_y"]) / ref["fwhm"] - 1), 5),
+                         "de_err_pct": round(100.0 * (m["de"] / ref["de"] - 1), 5),
+                         "mtf_err_pct": round(100.0 * (m["mtf_half_cut"] / ref["mtf"] - 1), 5)})
+            del ws, roi, plan
+            torch.cuda.empty_cache()
+        e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
+        rows[-2]["rel_l2_vs_fp64"] = e
+        log(f"convergence N={N}: {rows[-1]}; split rel-L2 vs fp64 {e:.2e}")
+    return {"workload": "binary FZP D=0.08 m f=1.5 m lambda=532 nm, ROI 512^2 at +-8 lambda f/#",
+            "reference": {k: round(v, 9) for k, v in ref.items()}, "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -362,6 +417,8 @@ def main():
         out["batch64"] = run_batch(args, dev)
     if not args.no_multilevel:
         out["ml100mm"] = run_multilevel(args, dev)
+    if args.convergence:
+        out["convergence"] = run_convergence(dev)
     if args.surrogate:
         from paper_2609_01978_amd import surrogate as SG
         sw = workload("surrogate")
