@@ -178,6 +178,27 @@ fzp_status_t fzp_propagate_roi_range(fzp_plan_t p, void *workspace, double *roi_
                                      int64_t row_begin, int64_t row_end, int32_t accumulate,
                                      void *stream);
 
+/* Resumable whole-aperture propagation with a checkpoint file on the host (the
+ * paper's long runs stream row chunks through files and skip verified groups on
+ * restart, Fig. 18 stage 2; here only the M x M float64 ROI and the next row are
+ * kept).  The rows run in blocks of rows_per_checkpoint (0: one chunk; rounded
+ * up to whole chunks, so the blocks end where the chunks of fzp_propagate_roi
+ * end); after each block the ROI buffer and the next row go to `path` (written
+ * as path + ".tmp", then renamed).  When `path` exists and carries this plan's
+ * fingerprint (aperture, instances, path, chunk, K-segment length and GEMM
+ * variant), the ROI is restored from it and the rows continue where it left
+ * off, so the finished ROI is bit for bit the one fzp_propagate_roi gives.
+ * max_rows > 0 stops after the first block that reaches max_rows rows in this
+ * call (a time-sliced run); *next_row (may be NULL) receives the row where the
+ * next call starts, N when the aperture is complete.  On completion the file
+ * is removed unless keep != 0.  Synchronous on `stream`.  Errors: FZP_E_INVAL
+ * for a checkpoint of another plan or a malformed file (the file is left in
+ * place), FZP_E_DEVICE when a file cannot be written. */
+fzp_status_t fzp_propagate_resumable(fzp_plan_t p, void *workspace, double *roi_dev,
+                                     const char *path, int64_t rows_per_checkpoint,
+                                     int64_t max_rows, int32_t keep, int64_t *next_row,
+                                     void *stream);
+
 /* Metrics of every instance from roi_dev (as written by fzp_propagate_roi),
  * computed on the device; out_host receives n_inst records.  Synchronises
  * `stream`.  Instances with M not a power of two in 8 .. 4096 get NaN MTF. */

@@ -39,7 +39,7 @@ FLAG_BIN_DEEP = 32
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
-    "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
+    "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
     "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
     "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
@@ -93,6 +93,13 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_01978_amd.build`")
+    # torch's HIP runtime goes first: it and the library's runtime carry the same
+    # soname, so the library then binds to the runtime that owns the device
+    # buffers instead of loading a second copy (which sees no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     st = ctypes.c_int32
     P = ctypes.c_void_p
@@ -111,6 +118,9 @@ def load_library() -> ctypes.CDLL:
     lib.fzp_propagate_roi.restype = st
     lib.fzp_propagate_roi_range.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
     lib.fzp_propagate_roi_range.restype = st
+    lib.fzp_propagate_resumable.argtypes = [P, P, P, ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int64), P]
+    lib.fzp_propagate_resumable.restype = st
     lib.fzp_metrics.argtypes = [P, P, P, ctypes.POINTER(Metrics), P]
     lib.fzp_metrics.restype = st
     lib.fzp_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -274,6 +284,17 @@ class Plan:
         _check(self._lib, self._lib.fzp_propagate_roi_range(self._h, _ptr(ws), _ptr(roi), int(row_begin),
                                                             int(row_end), int(bool(accumulate)),
                                                             _stream_handle(stream)))
+
+    def propagate_resumable(self, ws, roi, path: str, rows_per_checkpoint: int = 0, max_rows: int = 0,
+                            keep: bool = False, stream=None) -> int:
+        """fzp_propagate_resumable: whole aperture with a checkpoint file; returns
+        the row where the next call starts (N when complete)."""
+        nxt = ctypes.c_int64(0)
+        _check(self._lib, self._lib.fzp_propagate_resumable(self._h, _ptr(ws), _ptr(roi), os.fsencode(path),
+                                                            int(rows_per_checkpoint), int(max_rows),
+                                                            int(bool(keep)), ctypes.byref(nxt),
+                                                            _stream_handle(stream)))
+        return int(nxt.value)
 
     def profile(self, on: bool = True):
         """Bracket every row-pass and column-pass launch with HIP events."""

@@ -703,6 +703,113 @@ extern "C" fzp_status_t fzp_propagate_roi(fzp_plan_t h, void *workspace, double 
   return fzp_propagate_roi_range(h, workspace, roi_dev, 0, h->plan.ap.N, 0, stream);
 }
 
+namespace {
+
+// FNV-1a over everything that fixes the bits of a plan's ROI.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <typename T> void put(const T &v) { bytes(&v, sizeof(v)); }
+};
+
+uint64_t plan_fingerprint(const Plan &p) {
+  Fnv f;
+  f.put(p.ap.D), f.put(p.ap.f0), f.put(p.ap.lambda0), f.put(p.ap.pitch), f.put(p.ap.N);
+  f.put(p.ap.centre_open), f.put(p.ap.levels), f.put(p.opt.path), f.put(p.chunk_rows), f.put(p.seg_len);
+  f.put(p.bin_variant), f.put(p.roi_elems);
+  for (const auto &ih : p.inst) {
+    f.put(ih.in.lambda), f.put(ih.in.z), f.put(ih.in.x0), f.put(ih.in.y0), f.put(ih.in.half_width);
+    f.put(ih.in.M), f.put(ih.in.n_creases);
+    for (const auto &c : ih.creases) f.put(c.theta), f.put(c.offset), f.put(c.width), f.put(c.height);
+  }
+  return f.h;
+}
+
+constexpr char kCkptMagic[8] = {'F', 'Z', 'P', 'C', 'K', 'P', 'T', '1'};
+
+struct CkptHeader {
+  char magic[8];
+  uint64_t fingerprint;
+  int64_t roi_elems;  // complex elements
+  int64_t next_row;
+};
+
+}  // namespace
+
+extern "C" fzp_status_t fzp_propagate_resumable(fzp_plan_t h, void *workspace, double *roi_dev, const char *path,
+                                                int64_t rows_per_checkpoint, int64_t max_rows, int32_t keep,
+                                                int64_t *next_row, void *stream) {
+  if (!h || !workspace || !roi_dev || !path) return fail(FZP_E_INVAL, "fzp_propagate_resumable: NULL argument");
+  if (rows_per_checkpoint < 0 || max_rows < 0)
+    return fail(FZP_E_INVAL, "fzp_propagate_resumable: negative row count");
+  try {
+    Plan &p = h->plan;
+    const int64_t N = p.ap.N;
+    const int64_t chunk = p.chunk_rows > 0 ? p.chunk_rows : N;
+    int64_t block = rows_per_checkpoint > 0 ? rows_per_checkpoint : chunk;
+    block = (block + chunk - 1) / chunk * chunk;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t fp = plan_fingerprint(p);
+    const size_t nbytes = (size_t)p.roi_elems * 2 * sizeof(double);
+    std::vector<double> host((size_t)p.roi_elems * 2);
+    int64_t row = 0;
+    bool have_roi = false;
+    if (FILE *f = std::fopen(path, "rb")) {
+      CkptHeader hd;
+      const bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kCkptMagic, 8) == 0 &&
+                      hd.roi_elems == p.roi_elems && hd.next_row >= 0 && hd.next_row <= N &&
+                      (hd.next_row % chunk == 0 || hd.next_row == N) &&
+                      std::fread(host.data(), 1, nbytes, f) == nbytes;
+      std::fclose(f);
+      if (!ok) return fail(FZP_E_INVAL, std::string("fzp_propagate_resumable: malformed checkpoint ") + path);
+      if (hd.fingerprint != fp)
+        return fail(FZP_E_INVAL, std::string("fzp_propagate_resumable: ") + path + " belongs to another plan");
+      hipError_t e = hipMemcpyAsync(roi_dev, host.data(), nbytes, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_resumable: restore", e);
+      row = hd.next_row;
+      have_roi = true;
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    int64_t done = 0;
+    while (row < N && (max_rows == 0 || done < max_rows)) {
+      const int64_t r1 = row + block < N ? row + block : N;
+      fzp_status_t s = fzp_propagate_roi_range(h, workspace, roi_dev, row, r1, have_roi ? 1 : 0, stream);
+      if (s != FZP_OK) return s;
+      have_roi = true;
+      done += r1 - row;
+      row = r1;
+      hipError_t e = hipMemcpyAsync(host.data(), roi_dev, nbytes, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_resumable: checkpoint copy", e);
+      CkptHeader hd;
+      std::memcpy(hd.magic, kCkptMagic, 8);
+      hd.fingerprint = fp;
+      hd.roi_elems = p.roi_elems;
+      hd.next_row = row;
+      FILE *f = std::fopen(tmp.c_str(), "wb");
+      bool ok = f && std::fwrite(&hd, sizeof(hd), 1, f) == 1 && std::fwrite(host.data(), 1, nbytes, f) == nbytes;
+      if (f) ok = (std::fclose(f) == 0) && ok;
+      if (!ok || std::rename(tmp.c_str(), path) != 0)
+        return fail(FZP_E_DEVICE, std::string("fzp_propagate_resumable: cannot write ") + path);
+    }
+    if (!have_roi) {  // an aperture with no rows to run: the ROI is zero
+      const hipError_t e = fzp::launch_zero(roi_dev, 2 * p.roi_elems, st);
+      if (e != hipSuccess) return hip_fail("fzp_propagate_resumable: zero", e);
+    }
+    if (next_row) *next_row = row;
+    if (row >= N && !keep) std::remove(path);
+    return FZP_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(FZP_E_NOMEM, "fzp_propagate_resumable: out of host memory");
+  } catch (const std::exception &e) {
+    return fail(FZP_E_INVAL, std::string("fzp_propagate_resumable: ") + e.what());
+  }
+}
+
 extern "C" fzp_status_t fzp_metrics(fzp_plan_t h, void *workspace, const double *roi_dev, fzp_metrics_t *out_host,
                                     void *stream) {
   if (!h || !workspace || !roi_dev || !out_host) return fail(FZP_E_INVAL, "fzp_metrics: NULL argument");
