@@ -155,3 +155,19 @@ def test_missing_library_raises_import_error(monkeypatch):
         L.load_library()
     with pytest.raises(ImportError):
         P.Plan(dict(D=2e-3, f0=10e-3, lambda0=632.8e-9, N=256), [dict(lam=632.8e-9, M=16)])
+
+
+def test_phase_plate_plans():
+    """levels: 0 or 2 .. 64, amplitude-only centre_open; a split phase plate
+    takes the complex-stripe layout (stripe planes in the workspace)."""
+    from paper_2609_01978_amd._lib import FZPError
+    base = dict(D=2e-3, f0=10e-3, lambda0=632.8e-9, N=2048)
+    for bad in (dict(levels=1), dict(levels=65), dict(levels=-2), dict(levels=4, centre_open=1)):
+        with pytest.raises(FZPError) as ei:
+            P.Plan(dict(base, **bad), [dict(lam=632.8e-9, M=32)])
+        assert ei.value.status == L.FZP_E_INVAL
+    flat = P.Plan(base, [dict(lam=632.8e-9, M=64)], path="split")
+    for L in (2, 4, 16, 64):
+        ph = P.Plan(dict(base, levels=L), [dict(lam=632.8e-9, M=64)], path="split")
+        assert ph.workspace_size > flat.workspace_size
+        assert P.Plan(dict(base, levels=L), [dict(lam=632.8e-9, M=64)]).workspace_size > 0

@@ -87,13 +87,6 @@ def test_phase_plate_with_creases_and_chunks(path):
     assert e < (1e-9 if path == "fp64" else 1e-4)
 
 
-def test_invalid_levels_are_rejected():
-    for bad in (dict(levels=1), dict(levels=65), dict(levels=-2), dict(levels=4, centre_open=1)):
-        ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=256, **bad)
-        with pytest.raises(Exception):
-            P.Plan(ap, [dict(lam=LAM0, M=32)])
-
-
 @pytest.mark.parametrize("path", ["fp64", "split"])
 def test_ml100mm_sampled_stripes(path):
     """The benchmarked phase plate: 64-row stripes through the centre and near
