@@ -167,7 +167,7 @@ def test_phase_plate_plans():
             P.Plan(dict(base, **bad), [dict(lam=632.8e-9, M=32)])
         assert ei.value.status == L.FZP_E_INVAL
     flat = P.Plan(base, [dict(lam=632.8e-9, M=64)], path="split")
-    for L in (2, 4, 16, 64):
-        ph = P.Plan(dict(base, levels=L), [dict(lam=632.8e-9, M=64)], path="split")
+    for lv in (2, 4, 16, 64):
+        ph = P.Plan(dict(base, levels=lv), [dict(lam=632.8e-9, M=64)], path="split")
         assert ph.workspace_size > flat.workspace_size
-        assert P.Plan(dict(base, levels=L), [dict(lam=632.8e-9, M=64)]).workspace_size > 0
+        assert P.Plan(dict(base, levels=lv), [dict(lam=632.8e-9, M=64)]).workspace_size > 0
