@@ -198,6 +198,18 @@ struct CreasedRow {
     const double x0 = 0.5 * c0 * d->dx;
     bool open[16];
     double turns[16];
+    if (d->levels != 0 && d->n_creases == 0) {
+      // L-level phase plate without creases: the level's phasor from the table
+      const int L = d->levels;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const double ci = c0 + 512.0 * r;
+        const double K = ci * ci + bj;  // exact integer
+        const int lv = (int)(K * d->kappa_l) % L;
+        v[r] = t + 256 * r < cnt ? d->lev[lv] : make_double2(0.0, 0.0);
+      }
+      return;
+    }
     if (d->levels != 0) {
       // L-level phase plate: every disc sample passes, with the lens phase
       // quantised to level l = floor(K kappa_L) mod L, -l/L turns

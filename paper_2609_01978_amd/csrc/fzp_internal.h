@@ -51,6 +51,7 @@ struct InstDev {
   const double2 *Dt;       // e^{i pi (beta - alpha) n^2}, n < L
   const double2 *Qx, *Qy;  // e^{-i pi alpha d^2}
   const CreaseDev *cr;
+  const double2 *lev;      // phase plates: exp(-2 pi i l / L), l = 0 .. L-1
   const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
   const uint16_t *By;      // split path: column kernel matrix, [4 planes][Npad/16][M padded to 256][16] bf16
   int64_t Npad;

@@ -299,8 +299,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       off = align256(off + (size_t)ih.in.M * sizeof(double2));
       ih.off_Qy = off;
       off = align256(off + (size_t)ih.in.M * sizeof(double2));
-      ih.off_cr = off;
-      off = align256(off + (size_t)(ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
+      ih.off_cr = off;  // crease constants, then the phase-level phasors
+      off = align256(off + (size_t)(ih.creases.size() + 1) * sizeof(fzp::CreaseDev) + 64 * sizeof(double2));
       ih.table_owner = k;
       ih.col_owner = k;
       ih.off_A = 0;
@@ -433,6 +433,7 @@ void bind_tables(Plan &p, char *ws) {
     ih.dev.Qx = (const double2 *)(ws + ih.off_Qx);
     ih.dev.Qy = (const double2 *)(ws + ih.off_Qy);
     ih.dev.cr = (const fzp::CreaseDev *)(ws + ih.off_cr);
+    ih.dev.lev = (const double2 *)(ws + ih.off_cr + (ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
     ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
     ih.dev.By = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_By) : nullptr;
   }
@@ -464,6 +465,15 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
       hipError_t e = hipMemcpyAsync(ws + ih.off_cr, cd.data(), cd.size() * sizeof(fzp::CreaseDev),
                                     hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return hip_fail("fzp_prepare: crease upload", e);
+      // phase plates: the L level phasors exp(-2 pi i l / L) in float64
+      std::vector<double2> lev(64, make_double2(0.0, 0.0));
+      for (int l = 0; l < p.ap.levels; ++l) {
+        const double a = -2.0 * M_PI * (double)l / (double)p.ap.levels;
+        lev[l] = make_double2(std::cos(a), std::sin(a));
+      }
+      e = hipMemcpyAsync(ws + ih.off_cr + cd.size() * sizeof(fzp::CreaseDev), lev.data(), lev.size() * sizeof(double2),
+                         hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail("fzp_prepare: level upload", e);
       // pageable source: make sure the copy has consumed cd before it goes out of scope
       e = hipStreamSynchronize(st);
       if (e != hipSuccess) return hip_fail("fzp_prepare: synchronize", e);
