@@ -12,6 +12,12 @@ split-BF16 MFMA path, next to the float64 Bluestein path on the same GPU; the
 split result is valid only when its ROI intensity is within rel-L2 1e-4 of the
 float64 path's.  Inputs are synthetic and analytic (the zone plate itself).
 
+Besides the headline it reports, on the same GPU: the 64-instance creased
+batch of the 20 mm element (graph-launched, autotuned), the 0.1 m 4-level
+phase plate (``ml100mm``), the CPU oracle on a sample of the workload, and on
+request the grid-convergence sweep of the accuracy study (``--convergence``)
+and the learned surrogate (``--surrogate``).
+
 Prints exactly one JSON line.
 """
 from __future__ import annotations
