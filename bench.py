@@ -210,6 +210,24 @@ def run_multilevel(args, dev):
         I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
         res[path] = {"gsamples_s": round(samples / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
                      "de": m["de"], "fwhm_x": m["fwhm_x"], "strehl": m["strehl"]}
+        if path == "split":
+            # the row GEMM's own time (HIP events around its launches, one more
+            # propagation): 16 M flops per disc sample for a 2- or 4-level plate
+            # (hi planes only), 24 M otherwise
+            plan.profile(True)
+            plan.profile_read(reset=True)
+            plan.propagate(ws, roi)
+            torch.cuda.synchronize()
+            pr = plan.profile_read(reset=True)
+            plan.profile(False)
+            per = (16.0 if L in (2, 4) else 24.0) * w["M"]
+            flops = per * float(plan.info()["disc_samples"])
+            ach = flops / (pr["row_ms"] * 1e-3) / 1e12
+            res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS,
+                                         unit="TFLOP/s", frac=round(ach / PEAK_BF16_TFLOPS, 4),
+                                         kernel="k_row_pass_split_cplx", launch_ms=round(
+                                             pr["row_ms"] / max(pr["row_launches"], 1), 3),
+                                         work=f"{per / w['M']:.0f} M flops per disc sample")
         del ws, roi, plan
         torch.cuda.empty_cache()
     e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
