@@ -190,7 +190,14 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         float sn, cs;
-        sincos_turns(turns[e + u], sn, cs);
+        if constexpr (EXACT) {
+          // -l/L turns with L = 2 or 4: a whole number q of clockwise quarter turns
+          const int q = (int)rintf(-4.0f * turns[e + u]) & 3;
+          cs = q == 0 ? 1.0f : (q == 2 ? -1.0f : 0.0f);
+          sn = q == 3 ? 1.0f : (q == 1 ? -1.0f : 0.0f);
+        } else {
+          sincos_turns(turns[e + u], sn, cs);
+        }
         const bool o = (open >> (e + u)) & 1u;
         const float gr = o ? cs : 0.0f, gi = o ? sn : 0.0f;
         const uint16_t rh = bf16_cvt(gr), ih = bf16_cvt(gi);
