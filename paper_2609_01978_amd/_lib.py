@@ -30,6 +30,7 @@ STATUS_NAMES = {0: "FZP_OK", -1: "FZP_E_INVAL", -2: "FZP_E_SAMPLING", -3: "FZP_E
 
 PATH_FP64_BLUESTEIN = 0
 PATH_SPLIT_BF16 = 1
+PATH_AUTO = 2
 FLAG_ALLOW_UNDERSAMPLED = 1
 FLAG_BIN_TILE_256 = 2
 FLAG_BIN_SHALLOW = 4
@@ -212,7 +213,8 @@ class Plan:
             arr[k] = Instance(lambda_=inst["lam"], z=inst.get("z", 0.0), x0=inst.get("x0", 0.0),
                               y0=inst.get("y0", 0.0), half_width=inst.get("half_width", 0.0), M=int(inst["M"]),
                               n_creases=ncr, creases=ctypes.cast(cbuf, ctypes.POINTER(Crease)))
-        p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16}[path] if isinstance(path, str) else int(path)
+        p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16, "auto": PATH_AUTO}[path] \
+            if isinstance(path, str) else int(path)
         opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
                       flags=(FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0)
                       | {0: FLAG_BIN_SHALLOW, 1: FLAG_BIN_TILE_256, 2: FLAG_BIN_DEEP,

@@ -113,8 +113,24 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     *out = nullptr;
     fzp_options_t o{};
     if (opt) o = *opt;
-    if (o.path != FZP_PATH_FP64_BLUESTEIN && o.path != FZP_PATH_SPLIT_BF16)
+    if (o.path != FZP_PATH_FP64_BLUESTEIN && o.path != FZP_PATH_SPLIT_BF16 && o.path != FZP_PATH_AUTO)
       return fail(FZP_E_INVAL, "fzp_plan: unknown path");
+    if (o.path == FZP_PATH_AUTO) {
+      // the split GEMMs cost 8 M (binary), 16 M (2- and 4-level phase) or
+      // 24 M (complex) flops per sample, the FP64 Bluestein path a few hundred
+      // whatever M is: the measured crossovers on MI355X
+      int mmax = 0;
+      bool m16 = true, creased = false;
+      for (int k = 0; k < n_inst; ++k) {
+        mmax = inst[k].M > mmax ? inst[k].M : mmax;
+        m16 = m16 && inst[k].M % 16 == 0;
+        creased = creased || inst[k].n_creases > 0;
+      }
+      int limit = 128;
+      if (ap->levels == 0 && !creased) limit = 1024;
+      else if (ap->levels == 0 || ((ap->levels == 2 || ap->levels == 4) && !creased)) limit = 256;
+      o.path = m16 && mmax <= limit ? FZP_PATH_SPLIT_BF16 : FZP_PATH_FP64_BLUESTEIN;
+    }
     if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
       return fail(FZP_E_INVAL, "fzp_plan: D, f0 and lambda0 must be finite and positive");
     if (!(std::isfinite(ap->pitch) && ap->pitch >= 0.0)) return fail(FZP_E_INVAL, "fzp_plan: pitch must be >= 0");

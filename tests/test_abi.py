@@ -171,3 +171,17 @@ def test_phase_plate_plans():
         ph = P.Plan(dict(base, levels=lv), [dict(lam=632.8e-9, M=64)], path="split")
         assert ph.workspace_size > flat.workspace_size
         assert P.Plan(dict(base, levels=lv), [dict(lam=632.8e-9, M=64)]).workspace_size > 0
+
+
+@pytest.mark.parametrize("levels,creased,M,want", [
+    (0, False, 512, L.PATH_SPLIT_BF16), (0, False, 1024, L.PATH_SPLIT_BF16), (0, False, 2048, L.PATH_FP64_BLUESTEIN),
+    (0, True, 256, L.PATH_SPLIT_BF16), (0, True, 512, L.PATH_FP64_BLUESTEIN),
+    (4, False, 256, L.PATH_SPLIT_BF16), (4, False, 512, L.PATH_FP64_BLUESTEIN), (4, True, 256, L.PATH_FP64_BLUESTEIN),
+    (8, False, 128, L.PATH_SPLIT_BF16), (8, False, 256, L.PATH_FP64_BLUESTEIN),
+    (0, False, 100, L.PATH_FP64_BLUESTEIN)])
+def test_auto_path_follows_the_measured_crossover(levels, creased, M, want):
+    ap = dict(D=2e-3, f0=10e-3, lambda0=632.8e-9, N=4096, levels=levels)
+    inst = dict(lam=632.8e-9, M=M)
+    if creased:
+        inst["creases"] = [[0.3, 1e-4, 1e-4, 1e-7]]
+    assert P.Plan(ap, [inst], path="auto").info()["path"] == want
