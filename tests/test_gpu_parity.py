@@ -490,3 +490,15 @@ def test_random_shapes_both_paths(case):
     announce(f"  fp64 complex rel-L2 {e64:.2e}, split intensity rel-L2 {es:.2e}")
     assert e64 < 1e-9
     assert es <= 1e-4
+
+
+def test_auto_path_runs_the_chosen_path():
+    """path="auto" resolves at plan time and then runs exactly that path."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
+    inst = dict(lam=LAM0, M=128)
+    pa, _, _, (Ua,) = run_gpu(ap, [inst], path="auto")
+    _, _, _, (Us,) = run_gpu(ap, [inst], path="split")
+    assert pa.info()["path"] == 1 and np.array_equal(Ua, Us)
+    pf, _, _, (Uf,) = run_gpu(ap, [dict(lam=LAM0, M=2000)], path="auto")
+    _, _, _, (U6,) = run_gpu(ap, [dict(lam=LAM0, M=2000)], path="fp64")
+    assert pf.info()["path"] == 0 and np.array_equal(Uf, U6)
