@@ -70,3 +70,20 @@ def test_time_sliced_run_matches_one_call(tmp_path, path, lanes):
     torch.cuda.synchronize()
     assert nxt == AP["N"] and not os.path.exists(f)
     assert np.array_equal(roi.cpu().numpy(), ref)
+
+
+@pytest.mark.gpu
+def test_finished_checkpoint_restores_the_roi(tmp_path):
+    """keep=True leaves the finished checkpoint; a later call restores the ROI
+    from it without propagating and then removes it."""
+    torch = pytest.importorskip("torch")
+    plan = _plan("fp64")
+    ws, roi = plan.alloc()
+    f = str(tmp_path / "done.ckpt")
+    assert plan.propagate_resumable(ws, roi, f, keep=True) == AP["N"] and os.path.exists(f)
+    torch.cuda.synchronize()
+    ref = roi.cpu().numpy().copy()
+    roi.fill_(7.0)
+    assert _plan("fp64").propagate_resumable(ws, roi, f) == AP["N"]
+    torch.cuda.synchronize()
+    assert np.array_equal(roi.cpu().numpy(), ref) and not os.path.exists(f)
