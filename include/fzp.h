@@ -70,9 +70,10 @@ typedef int32_t fzp_status_t;
                                      chunks and the ROI in float64 */
 #define FZP_PATH_AUTO 2           /* fzp_plan picks one of the two by the crossover measured on
                                      MI355X: split when every M is a multiple of 16 and the
-                                     largest M is at most 1024 (binary plate), 256 (creased
-                                     amplitude plate, or 2- and 4-level phase plate), 128
-                                     (other phase plates); fzp_plan_info reports the choice */
+                                     largest M is at most 1024 (binary plate, or crease-free
+                                     2-level phase plate), 256 (creased amplitude plate, or
+                                     crease-free 4-level phase plate), 128 (other phase
+                                     plates); fzp_plan_info reports the choice */
 
 /* Plan flags. */
 #define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */

@@ -480,9 +480,12 @@ __global__ __launch_bounds__(256) void k_build_col_table(InstDev d, int64_t rows
 // outside [row_begin, row_end).  A work-group covers one 32-row block of kk and
 // 8 columns, so each wave reads two 128-byte runs of T and writes one
 // 128-byte run per plane (one 512-byte run per work-group).
+// With S (a 2-level plate) the partial planes hold T_mask and the operand is
+// T_disc - 2 T_mask, T_disc = S[hi] - S[lo] over row j's disc chord [lo, hi).
 __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, int64_t row_end,
                                                      const float *__restrict__ T, int nseg, int64_t seg_stride_f,
-                                                     int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb) {
+                                                     int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb,
+                                                     const double2 *__restrict__ S, int64_t N, double kmax) {
   const int64_t kk = blockIdx.x * (int64_t)32 + (threadIdx.x & 31);
   const int c = blockIdx.y * 8 + (threadIdx.x >> 5);
   if (kk >= KB || c >= M2) return;
@@ -501,6 +504,22 @@ __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, 
       v += (double)a3;
     }
     for (; sgi < nseg; ++sgi) v += (double)src[(int64_t)sgi * seg_stride_f];
+    if (S) {
+      const double cj = (double)(2 * j - N + 1);
+      const double rem = kmax - cj * cj;
+      double disc = 0.0;
+      if (rem >= 0.0) {
+        int64_t m = (int64_t)sqrt(rem);
+        while ((double)(m + 1) * (double)(m + 1) <= rem) ++m;
+        while (m > 0 && (double)m * (double)m > rem) --m;
+        int64_t lo = (N - 1 - m + 1) >> 1, hi = ((N - 1 + m) >> 1) + 1;
+        if (lo < 0) lo = 0;  // a disc wider than the grid
+        if (hi > N) hi = N;
+        const double2 a = S[hi * (M2 / 2) + (c >> 1)], b = S[lo * (M2 / 2) + (c >> 1)];
+        disc = (c & 1) ? a.y - b.y : a.x - b.x;
+      }
+      v = disc - 2.0 * v;
+    }
     h = bf16_rne((float)v);
     l = bf16_rne((float)(v - (double)__uint_as_float((uint32_t)h << 16)));
   }
@@ -658,6 +677,83 @@ size_t col_partial_bytes(int M) {
   return (size_t)target * (size_t)M * (size_t)(2 * M) * sizeof(float);
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// 2-level phase plates: prefix sums of the row kernel along the aperture row.
+// S[i][q] = sum_{i' < i} A(i', q), A(i, q) = e^{2 pi i (beta c_i^2/2 - alpha c_i d_q)}
+// in float64 (the same turns as the operand table, unsplit), by blocks of
+// kPrefixBlock rows: local running sums, an exclusive scan of the block totals
+// per column, then the offsets added; a fixed order, so the table is the same
+// on every build.
+// ---------------------------------------------------------------------------
+constexpr int kPrefixBlock = 2048;
+
+__global__ __launch_bounds__(256) void k_prefix_local(InstDev d, double2 *__restrict__ S, double2 *__restrict__ tot) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  const int M = d.M;
+  if (q >= M) return;
+  const double dq = (double)q - 0.5 * (double)M + d.sx;
+  const int64_t i0 = b * kPrefixBlock;
+  const int64_t i1 = i0 + kPrefixBlock < d.N ? i0 + kPrefixBlock : d.N;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t i = i0; i < i1; ++i) {
+    const double c = (double)i - 0.5 * (double)(d.N - 1);
+    const double ph = 0.5 * d.beta * (c * c);
+    const double lin = d.alpha * c * dq;
+    acc = cadd(acc, cexp_turns((ph - rint(ph)) - (lin - rint(lin))));
+    S[(i + 1) * M + q] = acc;
+  }
+  tot[b * M + q] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_prefix_offsets(int M, int64_t nb, double2 *__restrict__ tot,
+                                                        double2 *__restrict__ S) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  double2 off = make_double2(0.0, 0.0);
+  for (int64_t b = 0; b < nb; ++b) {
+    const double2 t = tot[b * M + q];
+    tot[b * M + q] = off;
+    off = cadd(off, t);
+  }
+  S[q] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_prefix_add(int M, int64_t N, const double2 *__restrict__ tot,
+                                                    double2 *__restrict__ S) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // element (i, q) of rows 1 .. N
+  if (e >= N * (int64_t)M) return;
+  const int64_t i = e / M;
+  const int q = (int)(e - i * M);
+  S[(i + 1) * M + q] = cadd(S[(i + 1) * M + q], tot[(i / kPrefixBlock) * M + q]);
+}
+
+}  // namespace
+
+bool two_level_fast(const InstDev &d) { return d.levels == 2 && d.n_creases == 0 && d.S != nullptr; }
+
+size_t prefix_table_bytes(int M, int64_t Npad) {
+  const int64_t nb = (Npad + kPrefixBlock - 1) / kPrefixBlock;
+  return (size_t)(Npad + 1 + nb) * (size_t)M * sizeof(double2);
+}
+
+hipError_t launch_build_prefix_table(const InstDev &d, double2 *S, hipStream_t st) {
+  const int M = d.M;
+  const int64_t nb = (d.N + kPrefixBlock - 1) / kPrefixBlock;
+  double2 *tot = S + (d.Npad + 1) * (int64_t)M;  // block totals, then offsets
+  hipLaunchKernelGGL(k_prefix_local, dim3((unsigned)((M + 255) / 256), (unsigned)nb), dim3(256), 0, st, d, S, tot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prefix_offsets, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, nb, tot, S);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = d.N * (int64_t)M;
+  hipLaunchKernelGGL(k_prefix_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, d.N, tot, S);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st) {
   const int64_t rows_pad = (d.M + kCTR - 1) / kCTR * kCTR;
   const dim3 grid((unsigned)((d.Npad + 255) / 256), (unsigned)rows_pad);
@@ -673,7 +769,8 @@ hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t ro
   // T -> BF16 hi/lo operand (the row-pass partial planes: column stride = chunk rows)
   const int64_t rs = seg_stride / M;
   hipLaunchKernelGGL(k_col_operand, dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
-                     row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb);
+                     row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
+                     two_level_fast(d) ? d.S : nullptr, d.N, d.kmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = init_split_attributes();

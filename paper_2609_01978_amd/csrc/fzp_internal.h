@@ -52,6 +52,8 @@ struct InstDev {
   const double2 *Qx, *Qy;  // e^{-i pi alpha d^2}
   const CreaseDev *cr;
   const double2 *lev;      // phase plates: exp(-2 pi i l / L), l = 0 .. L-1
+  const double2 *S;        // split path, 2-level plate: prefix sums over i of the row kernel,
+                           // S[i][q] = sum_{i' < i} e^{2 pi i (beta c_i'^2/2 - alpha c_i' d_q)}, (Npad+1) x M
   const uint16_t *A;       // split path: [2 planes][2M cols][Npad] bf16
   const uint16_t *By;      // split path: column kernel matrix, [4 planes][Npad/16][M padded to 256][16] bf16
   int64_t Npad;
@@ -68,7 +70,7 @@ struct InstHost {
   std::vector<fzp_crease_t> creases;
   double lam, z, hw, dx_out;
   InstDev dev;
-  size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A, off_By;
+  size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A, off_By, off_S;
   int64_t roi_off;     // complex elements
   int32_t table_owner; // instance whose split table this one shares (itself if none)
   int32_t col_owner;   // instance whose column table (B_y) this one shares (itself if none)
@@ -150,6 +152,13 @@ size_t col_table_bytes(int M, int64_t Npad);
 size_t col_operand_bytes(int M, int64_t chunk_rows);
 size_t col_partial_bytes(int M);
 hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st);
+// 2-level phase plates on the split path (fzp_cplx.hip): t = disc - 2 mask
+// (mask = the odd zones), so T = T_disc - 2 T_mask with T_mask from the binary
+// GEMM and T_disc = S[hi] - S[lo] over each row's disc chord from float64
+// prefix sums of the row kernel (prefix_table_bytes, built once per workspace).
+bool two_level_fast(const InstDev &d);
+size_t prefix_table_bytes(int M, int64_t Npad);
+hipError_t launch_build_prefix_table(const InstDev &d, double2 *S, hipStream_t st);
 hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
                                  int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st);
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,

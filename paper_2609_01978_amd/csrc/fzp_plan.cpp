@@ -127,8 +127,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         creased = creased || inst[k].n_creases > 0;
       }
       int limit = 128;
-      if (ap->levels == 0 && !creased) limit = 1024;
-      else if (ap->levels == 0 || ((ap->levels == 2 || ap->levels == 4) && !creased)) limit = 256;
+      if ((ap->levels == 0 || ap->levels == 2) && !creased) limit = 1024;  // binary GEMM
+      else if (ap->levels == 0 || (ap->levels == 4 && !creased)) limit = 256;
       o.path = m16 && mmax <= limit ? FZP_PATH_SPLIT_BF16 : FZP_PATH_FP64_BLUESTEIN;
     }
     if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
@@ -252,7 +252,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     }
     bool cplx = false;  // split path with complex stripes (creases or a phase plate)
     if (split)
-      for (const auto &ih : p.inst) cplx = cplx || ih.in.n_creases > 0 || ap->levels != 0;
+      for (const auto &ih : p.inst)
+        cplx = cplx || ih.in.n_creases > 0 || (ap->levels != 0 && ap->levels != 2);
     if (split)
       for (const auto &ih : p.inst)
         if (ih.in.M % 16 != 0) {
@@ -321,6 +322,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       ih.col_owner = k;
       ih.off_A = 0;
       ih.off_By = 0;
+      ih.off_S = 0;
     }
     if (split) {
       const int64_t npad = (N + 63) / 64 * 64;
@@ -339,6 +341,12 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         if (ih.table_owner == k) {
           ih.off_A = off;
           off = align256(off + (size_t)2 * 2 * ih.in.M * npad * sizeof(uint16_t));
+          if (ap->levels == 2) {  // 2-level plates: prefix sums of the same kernel
+            ih.off_S = off;
+            off = align256(off + fzp::prefix_table_bytes(ih.in.M, npad));
+          }
+        } else {
+          ih.off_S = p.inst[ih.table_owner].off_S;
         }
         // the column pass's kernel matrix B_y: shared on the same terms, with the y shift
         for (int k2 = 0; k2 < k; ++k2) {
@@ -452,6 +460,7 @@ void bind_tables(Plan &p, char *ws) {
     ih.dev.lev = (const double2 *)(ws + ih.off_cr + (ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
     ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
     ih.dev.By = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_By) : nullptr;
+    ih.dev.S = p.opt.path == FZP_PATH_SPLIT_BF16 && p.ap.levels == 2 ? (const double2 *)(ws + ih.off_S) : nullptr;
   }
 }
 
@@ -498,6 +507,10 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
       if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.table_owner == (int32_t)k) {
         e = fzp::launch_build_split_table(p, ih, ws, st);
         if (e != hipSuccess) return hip_fail("fzp_prepare: split table kernel", e);
+        if (ih.dev.S) {
+          e = fzp::launch_build_prefix_table(ih.dev, (double2 *)(ws + ih.off_S), st);
+          if (e != hipSuccess) return hip_fail("fzp_prepare: prefix table kernel", e);
+        }
       }
       if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.col_owner == (int32_t)k) {
         e = fzp::launch_build_col_table(ih.dev, (uint16_t *)(ws + ih.off_By), st);
@@ -564,7 +577,9 @@ hipError_t ensure_aux(Plan &p) {
 fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2 *roi, int64_t row_begin,
                               int64_t row_end, hipStream_t st) {
   const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
-  const bool cplx = split && (ih.dev.n_creases > 0 || ih.dev.levels != 0);
+  // complex stripes: creases, or a phase plate other than the 2-level one
+  // (which runs as disc - 2 mask on the binary kernels)
+  const bool cplx = split && (ih.dev.n_creases > 0 || (ih.dev.levels != 0 && !fzp::two_level_fast(ih.dev)));
   void *T = ws + p.off_T[lane];
   hipError_t e;
   // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples

@@ -177,6 +177,7 @@ def test_phase_plate_plans():
     (0, False, 512, L.PATH_SPLIT_BF16), (0, False, 1024, L.PATH_SPLIT_BF16), (0, False, 2048, L.PATH_FP64_BLUESTEIN),
     (0, True, 256, L.PATH_SPLIT_BF16), (0, True, 512, L.PATH_FP64_BLUESTEIN),
     (4, False, 256, L.PATH_SPLIT_BF16), (4, False, 512, L.PATH_FP64_BLUESTEIN), (4, True, 256, L.PATH_FP64_BLUESTEIN),
+    (2, False, 1024, L.PATH_SPLIT_BF16), (2, False, 2048, L.PATH_FP64_BLUESTEIN), (2, True, 256, L.PATH_FP64_BLUESTEIN),
     (8, False, 128, L.PATH_SPLIT_BF16), (8, False, 256, L.PATH_FP64_BLUESTEIN),
     (0, False, 100, L.PATH_FP64_BLUESTEIN)])
 def test_auto_path_follows_the_measured_crossover(levels, creased, M, want):

@@ -131,3 +131,37 @@ def test_ml100mm_whole_plate_efficiency():
     assert abs(m6["de"] / ladder - 1) < 2e-4
     assert abs(m6["de"] / h["de"] - 1) < 2e-4
     assert abs(m6["fwhm_x"] / h["fwhm"] - 1) < 1e-2
+
+
+def test_two_level_plate_on_the_binary_kernels():
+    """A crease-free 2-level plate runs on the split path as disc - 2 mask: the
+    binary-stripe GEMM for the odd-zone mask and float64 prefix sums of the row
+    kernel for the disc.  The 0.1 m plate at L = 2: sampled stripes against the
+    oracle, the whole plate against the FP64 path and the ladder value
+    sinc^2(1/2) * 0.837785."""
+    w = workload("ml100mm")
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"], levels=2)
+    inst = dict(lam=w["lambda0"], M=w["M"])
+    plan = P.Plan(ap, [inst], path="split", stripe_rows=w["stripe"])
+    ws, roi = plan.alloc()
+    a, i = oracle(ap, inst)
+    N = w["N"]
+    for j0 in (N // 2 - 32, 7001):
+        plan.propagate_range(ws, roi, j0, j0 + 64, accumulate=False)
+        torch.cuda.synchronize()
+        U = plan.roi_view(roi, 0).cpu().numpy()
+        ref = O.propagate(a, i, rows=(j0, j0 + 64), stripe=32)
+        e = rel_l2(U, ref)
+        announce(f"  L=2 split rows {j0}..{j0 + 64}: complex rel-L2 {e:.2e}")
+        assert e <= 1e-4
+    plan.propagate(ws, roi)
+    ms = plan.metrics(ws, roi)[0]
+    Us = plan.roi_view(roi, 0).cpu().numpy()
+    p6, ws6, roi6, (U6,) = run(ap, [inst], "fp64")
+    m6 = p6.metrics(ws6, roi6)[0]
+    e = rel_l2(O.intensity(Us), O.intensity(U6))
+    ladder = (2.0 / math.pi) ** 2 * O.AIRY_LOBE_FRACTION
+    announce(f"  L=2 whole plate: split vs fp64 intensity {e:.2e}; DE split {ms['de']:.6f} fp64 {m6['de']:.6f} "
+             f"ladder {ladder:.6f}")
+    assert e <= 1e-4
+    assert abs(m6["de"] / ladder - 1) < 1e-3
