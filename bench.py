@@ -13,8 +13,9 @@ split result is valid only when its ROI intensity is within rel-L2 1e-4 of the
 float64 path's.  Inputs are synthetic and analytic (the zone plate itself).
 
 Besides the headline it reports, on the same GPU: the 64-instance creased
-batch of the 20 mm element (graph-launched, autotuned), the 0.1 m 4-level
-phase plate (``ml100mm``), the CPU oracle on a sample of the workload, and on
+batch of the 20 mm element (graph-launched, autotuned), the 0.1 m 4- and
+2-level phase plates (``ml100mm``, ``ml100mm_l2``), the CPU oracle on a
+sample of the workload, and on
 request the grid-convergence sweep of the accuracy study (``--convergence``)
 and the learned surrogate (``--surrogate``).
 
@@ -175,9 +176,10 @@ def run_batch(args, dev):
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_batch"] / res["split"]["ms_per_batch"], 3)}
 
 
-def run_multilevel(args, dev):
-    """The 0.1 m f/5 4-level phase plate (the revised engine's kind of element)
-    on both paths: one propagation plus metrics per step.  Valid when the split
+def run_multilevel(args, dev, levels=None):
+    """The 0.1 m f/5 L-level phase plate (the revised engine's kind of element;
+    L = 4 by default, 2 for the 2-level shortcut) on both paths: one
+    propagation plus metrics per step.  Valid when the split
     intensity is within rel-L2 1e-4 of the FP64 path's; the main-lobe DE is
     reported next to the L-level ladder value sinc^2(1/L) times the Airy lobe
     share 1 - J0(j_{1,1})^2."""
@@ -188,7 +190,7 @@ def run_multilevel(args, dev):
     import paper_2609_01978_amd as P
     from fzp_inputs import workload
     w = workload("ml100mm")
-    L = w["levels"]
+    L = w["levels"] if levels is None else levels
     ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"], levels=L)
     inst = dict(lam=w["lambda0"], M=w["M"])
     samples = float(w["N"]) ** 2
@@ -206,26 +208,28 @@ def run_multilevel(args, dev):
             m = plan.metrics(ws, roi)[0]
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.multilevel_steps
-        log(f"ml100mm {path}: {dt * 1e3:.1f} ms per propagation")
+        log(f"ml100mm L={L} {path}: {dt * 1e3:.1f} ms per propagation")
         I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
         res[path] = {"gsamples_s": round(samples / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
                      "de": m["de"], "fwhm_x": m["fwhm_x"], "strehl": m["strehl"]}
         if path == "split":
             # the row GEMM's own time (HIP events around its launches, one more
-            # propagation): 16 M flops per disc sample for a 2- or 4-level plate
-            # (hi planes only), 24 M otherwise
+            # propagation): 8 M flops per disc sample for a 2-level plate (the
+            # binary GEMM of its odd zones), 16 M for a 4-level plate (hi planes
+            # only), 24 M otherwise
             plan.profile(True)
             plan.profile_read(reset=True)
             plan.propagate(ws, roi)
             torch.cuda.synchronize()
             pr = plan.profile_read(reset=True)
             plan.profile(False)
-            per = (16.0 if L in (2, 4) else 24.0) * w["M"]
+            per = (8.0 if L == 2 else 16.0 if L == 4 else 24.0) * w["M"]
             flops = per * float(plan.info()["disc_samples"])
             ach = flops / (pr["row_ms"] * 1e-3) / 1e12
             res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS,
                                          unit="TFLOP/s", frac=round(ach / PEAK_BF16_TFLOPS, 4),
-                                         kernel="k_row_pass_split_cplx", launch_ms=round(
+                                         kernel="k_row_pass_split" if L == 2 else "k_row_pass_split_cplx",
+                                         launch_ms=round(
                                              pr["row_ms"] / max(pr["row_launches"], 1), 3),
                                          work=f"{per / w['M']:.0f} M flops per disc sample")
         del ws, roi, plan
@@ -441,6 +445,7 @@ def main():
         out["batch64"] = run_batch(args, dev)
     if not args.no_multilevel:
         out["ml100mm"] = run_multilevel(args, dev)
+        out["ml100mm_l2"] = run_multilevel(args, dev, levels=2)
     if args.convergence:
         out["convergence"] = run_convergence(dev)
     if args.surrogate:
