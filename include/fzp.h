@@ -88,7 +88,9 @@ typedef int32_t fzp_status_t;
 #define FZP_FLAG_BIN_DEEP 32          /* variant 2: 512-row tile with an 8-stage LDS pipeline */
 #define FZP_FLAG_OVERLAP_OPERAND 16   /* split path: make each chunk's stripe operand on an internal
                                          auxiliary stream one chunk ahead of its GEMM (two operand
-                                         buffers; not inside fzp_graph_create's capture) */
+                                         buffers); not under stream capture: fzp_graph_create,
+                                         or a call on a capturing stream, returns
+                                         FZP_E_UNSUPPORTED for such a plan */
 
 typedef struct {
   double D;          /* aperture diameter */
@@ -125,7 +127,8 @@ typedef struct {
 typedef struct {
   int32_t path;         /* FZP_PATH_* */
   int32_t stripe_rows;  /* rows per stripe, the row-pass work unit; 0 = path default */
-  int64_t chunk_rows;   /* rows transformed between two column passes; 0 = automatic: the
+  int64_t chunk_rows;   /* rows transformed between two column passes (values above N
+                           are taken as N); 0 = automatic: the
                            row-pass partial sums near 1 GiB (split) or 0.5 GiB (FP64); for
                            creased instances on the split path the complex stripe planes
                            near 2 GiB, grown up to 8 GiB while the GEMM grid of the
@@ -235,7 +238,8 @@ fzp_status_t fzp_profile_read(fzp_plan_t p, double *row_ms, int64_t *row_launche
  * must stay allocated while the graph lives; fzp_graph_launch replays it on
  * `stream` as one launch.  The workspace is prepared first (synchronously).
  * Kernel timing (fzp_profile_*) is not recorded inside a graph.  Errors:
- * FZP_E_INVAL, FZP_E_DEVICE. */
+ * FZP_E_INVAL, FZP_E_DEVICE, FZP_E_UNSUPPORTED (a split plan with
+ * FZP_FLAG_OVERLAP_OPERAND; checked before any device call). */
 typedef struct fzp_graph_s *fzp_graph_t;
 fzp_status_t fzp_graph_create(fzp_plan_t p, void *workspace, double *roi_dev, fzp_graph_t *out);
 fzp_status_t fzp_graph_launch(fzp_graph_t g, void *stream);

@@ -220,7 +220,14 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       d.B = fzp::kFftLen - in.M + 1;
       d.n_creases = in.n_creases;
       d.dx = p.dx;
-      d.alpha = p.dx * ih.dx_out / lz;
+      // alpha = dx dx_out / (lambda z); at the default pitch (D/N) and ROI
+      // (hw = 8 lambda z / D) it is 16 / (N M), formed from the integers (exact
+      // when N M is a power of two), so the Bluestein chirp turns alpha k^2 / 2
+      // carry no rounding of dx, dx_out or lambda z
+      if (ap->pitch == 0.0 && in.half_width == 0.0)
+        d.alpha = 16.0 / ((double)N * (double)in.M);
+      else
+        d.alpha = p.dx * ih.dx_out / lz;
       d.beta = p.dx * p.dx / lz;
       d.sx = in.x0 / ih.dx_out;
       d.sy = in.y0 / ih.dx_out;
@@ -278,7 +285,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
     const size_t tbytes = split ? sizeof(float) * 2 * (size_t)nseg : sizeof(double) * 2;
     if (o.chunk_rows > 0) {
-      p.chunk_rows = o.chunk_rows;
+      // more rows than the aperture has only enlarge the buffers (and could
+      // overflow the byte counts below): at most N
+      p.chunk_rows = o.chunk_rows < N ? o.chunk_rows : N;
     } else {
       const size_t budget = (size_t)(split ? 1024 : 512) << 20;  // T buffer target
       int64_t c = (int64_t)(budget / ((size_t)p.Mmax * tbytes));
@@ -618,9 +627,19 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     p.ev_marks.emplace_back(first, kind);
     return pe;
   };
-  // Without FZP_FLAG_OVERLAP_OPERAND, and always under graph capture, the
-  // operand is made on st itself, one chunk at a time.
-  const bool overlap = split && !p.capturing && (p.opt.flags & FZP_FLAG_OVERLAP_OPERAND);
+  // Without FZP_FLAG_OVERLAP_OPERAND the operand is made on st itself, one
+  // chunk at a time.
+  const bool overlap = split && (p.opt.flags & FZP_FLAG_OVERLAP_OPERAND);
+  if (overlap) {
+    // the overlap is not supported under stream capture: a capture of it
+    // (fzp_graph_create) ended in a host segmentation fault whose cause was
+    // not found, so a capturing stream gets an error instead
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: capture status", e);
+    if (p.capturing || cs != hipStreamCaptureStatusNone)
+      return fail(FZP_E_UNSUPPORTED, "fzp_propagate_roi_range: FZP_FLAG_OVERLAP_OPERAND under stream capture");
+  }
   hipStream_t ax = st;
   hipEvent_t *ev = nullptr;  // [0] fork, [1 + b] stripe b ready, [3 + b] GEMM done with buffer b
   auto stripe = [&](size_t i) -> hipError_t {
@@ -936,6 +955,10 @@ extern "C" fzp_status_t fzp_graph_create(fzp_plan_t h, void *workspace, double *
   if (!h || !workspace || !roi_dev || !out) return fail(FZP_E_INVAL, "fzp_graph_create: NULL argument");
   *out = nullptr;
   Plan &p = h->plan;
+  // a capture with the operand overlap ended in a host segmentation fault
+  // (cause not found): refused before any device call
+  if (p.opt.path == FZP_PATH_SPLIT_BF16 && (p.opt.flags & FZP_FLAG_OVERLAP_OPERAND))
+    return fail(FZP_E_UNSUPPORTED, "fzp_graph_create: FZP_FLAG_OVERLAP_OPERAND cannot be captured");
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail("fzp_graph_create: stream", e);

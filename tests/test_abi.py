@@ -186,3 +186,28 @@ def test_auto_path_follows_the_measured_crossover(levels, creased, M, want):
     if creased:
         inst["creases"] = [[0.3, 1e-4, 1e-4, 1e-7]]
     assert P.Plan(ap, [inst], path="auto").info()["path"] == want
+
+
+@pytest.mark.parametrize("path", ["fp64", "split"])
+def test_chunk_rows_above_n_are_taken_as_n(path):
+    """A caller's chunk_rows beyond the aperture only enlarges the buffers; a
+    huge value must not wrap the workspace byte counts: it is taken as N."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096)
+    inst = [dict(lam=LAM0, M=256)]
+    whole = P.Plan(ap, inst, path=path, chunk_rows=4096)
+    for c in (4097, 1 << 40, (1 << 62) + 12345):
+        p = P.Plan(ap, inst, path=path, chunk_rows=c)
+        assert p.info()["chunk_rows"] == whole.info()["chunk_rows"] == 4096
+        assert p.workspace_size == whole.workspace_size
+
+
+def test_graph_of_overlap_operand_plan_is_refused():
+    """fzp_graph_create refuses a split plan with FZP_FLAG_OVERLAP_OPERAND before
+    any device call (its capture is not supported)."""
+    lib = P.load_library()
+    plan = P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048), [dict(lam=LAM0, M=64)], path="split",
+                  overlap_operand=True)
+    g = ctypes.c_void_p()
+    st = lib.fzp_graph_create(plan._h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), ctypes.byref(g))
+    assert st == L.FZP_E_UNSUPPORTED and not g.value
+    assert b"OVERLAP_OPERAND" in lib.fzp_last_error()

@@ -157,3 +157,49 @@ def test_overlap_operand_reproduces():
         torch.cuda.synchronize()
         outs.append(roi.clone())
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("path,tol", [("fp64", 1e-9), ("split", 1e-4)])
+def test_graph_batch_against_oracle(path, tol):
+    """A graph-launched two-lane batch of mixed ROI sizes (64, 128, 256), flat and
+    creased, at N = 2048: every instance's whole ROI against the oracle's
+    Bluestein evaluation of Eq. 2 (complex rel-L2 for the FP64 path, intensity
+    rel-L2 for the split path)."""
+    ap, insts = small_batch()
+    plan = P.Plan(ap, insts, path=path, lanes=2)
+    ws, roi = plan.alloc()
+    g = plan.graph(ws, roi)
+    roi.fill_(float("nan"))
+    torch.cuda.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    oa = O.Aperture(D=ap["D"], f0=ap["f0"], lambda0=ap["lambda0"], N=ap["N"])
+    for k, (U, inst) in enumerate(zip(views(plan, roi), insts)):
+        ref = O.propagate(oa, O.Instance(lam=inst["lam"], M=inst["M"], creases=inst.get("creases")),
+                          method="bluestein", stripe=512)
+        e = rel_l2(U, ref) if path == "fp64" else rel_l2(O.intensity(U), O.intensity(ref))
+        announce(f"graph batch {path} instance {k} M={inst['M']} creased={'creases' in inst} rel-L2 {e:.2e}")
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.skip(reason="capturing a plan with FZP_FLAG_OVERLAP_OPERAND ended in a host segmentation "
+                         "fault inside fzp_graph_create, also with the auxiliary streams made before the "
+                         "capture; the cause is not found, so the library refuses the combination "
+                         "(FZP_E_UNSUPPORTED, tested on the CPU) and this case stays off the GPU")
+def test_graph_with_overlap_operand_matches_eager():
+    """FZP_FLAG_OVERLAP_OPERAND under graph capture: the auxiliary streams are
+    made before the capture; the replays equal the eager single-stream result."""
+    ap, insts = small_batch()
+    ref = P.Plan(ap, insts, path="split", chunk_rows=512)
+    wsr, roir = ref.alloc()
+    ref.propagate(wsr, roir)
+    plan = P.Plan(ap, insts, path="split", chunk_rows=512, lanes=2, overlap_operand=True)
+    ws, roi = plan.alloc()
+    announce("graph capture with overlap_operand")
+    g = plan.graph(ws, roi)
+    for rep in range(2):
+        roi.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(roi, roir), rep

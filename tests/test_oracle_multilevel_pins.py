@@ -88,6 +88,14 @@ def test_efficiency_ladder_at_many_zones(L):
     assert abs(h["fwhm"] / (O.AIRY_FWHM * lz / ap.D) - 1) < 1e-4
 
 
+@pytest.mark.parametrize("L", [2, 4, 8])
+def test_strehl_tends_to_sinc2(L):
+    """An L-step kinoform keeps sinc^2(1/L) of an ideal lens's focal peak
+    (pi R^2/(lambda z))^2 at many zones: the Strehl of the radial integral."""
+    ap = O.Aperture(D=0.02, f0=0.1, lambda0=LAM0, N=2, levels=L)
+    assert abs(O.hankel_metrics(ap)["strehl"] / sinc2(L) - 1) < 2e-4
+
+
 @pytest.mark.parametrize("L,N", [(4, 4096), (2, 2048)])
 def test_grid_matches_hankel(L, N):
     """The 2-D sampled plate against the continuous radial integral."""

@@ -48,6 +48,8 @@ def _pins():
         ("ml_two", mpins.test_two_levels_is_open_minus_closed_amplitude_plate),
         ("ml_ladder", lambda: mpins.test_efficiency_ladder_at_many_zones(4)),
         ("ml_axis", mpins.test_small_grid_on_axis_matches_hankel),
+        ("strehl", pins.test_strehl_is_the_share_of_an_ideal_lens_peak),
+        ("ml_strehl", lambda: mpins.test_strehl_tends_to_sinc2(4)),
     ]
 
 
@@ -191,6 +193,18 @@ def m_intervals_phase_sign(ap, s_max):
     return lo, hi, np.conj(t)
 
 
+def m_metrics_strehl_no_pi2(U_or_I, ap, inst, p_in_count=None):
+    m = ORIG["metrics"](U_or_I, ap, inst, p_in_count)
+    m["strehl"] *= math.pi ** 2                         # peak over (R^2/(lambda z))^2
+    return m
+
+
+def m_hankel_strehl_no_pi2(ap, lam=None, z=None, nodes=16, lobe_nodes=96):
+    h = ORIG["hankel_metrics"](ap, lam, z, nodes, lobe_nodes)
+    h["strehl"] *= math.pi ** 2
+    return h
+
+
 MUTANTS = {
     "czt_bluestein": m_bluestein_post_chirp_sign,
     "czt_direct": m_czt_direct_a_sign,
@@ -217,6 +231,8 @@ MUTANTS = {
     "phase_level/kappa": m_level_kappa_full_l,
     "aperture_field/phase_sign": m_field_phase_sign,
     "_open_zone_intervals/phase_sign": m_intervals_phase_sign,
+    "metrics/strehl": m_metrics_strehl_no_pi2,
+    "hankel_metrics/strehl": m_hankel_strehl_no_pi2,
 }
 
 

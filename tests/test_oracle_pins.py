@@ -312,6 +312,26 @@ def test_hankel_tends_to_airy_at_many_zones():
     assert abs(h["de"] / (O.AIRY_LOBE_FRACTION / math.pi ** 2) - 1) < 2e-4
 
 
+def test_strehl_is_the_share_of_an_ideal_lens_peak():
+    """Strehl = peak / (pi R^2/(lambda z))^2, where pi R^2/(lambda z) is the focal
+    field of an ideal lens of radius R (the disc area over lambda z).  A binary
+    plate whose last zone is opaque has n_open full open zones, each adding 2 to
+    the axial amplitude, so pi^2 Strehl = (2 n_open / N_F)^2 -> 1 (the 1/pi^2 of
+    a binary amplitude plate); the 2-D grid gives the same within its sampling
+    error."""
+    ap = O.Aperture(D=0.02, f0=0.1, lambda0=LAM0, N=2)
+    nf = (0.5 * ap.D) ** 2 / (LAM0 * ap.f0)                    # 1580.28 zones
+    n_open = int(nf) // 2                                       # zones 1, 3, .., 1579; zone 1580 is opaque
+    assert int(nf) % 2 == 0
+    want = (2 * n_open / nf) ** 2
+    assert abs(O.hankel_metrics(ap)["strehl"] * math.pi ** 2 - want) < 1e-6
+    ap = O.Aperture(D=2e-3, f0=10e-3, lambda0=LAM0, N=1024)      # 158.03 zones, 1.6 samples per outer zone
+    nf = (0.5 * ap.D) ** 2 / (LAM0 * ap.f0)
+    inst = O.Instance(lam=LAM0, M=32)
+    m = O.metrics(O.propagate(ap, inst, stripe=512), ap, inst)
+    assert abs(m["strehl"] * math.pi ** 2 - (2 * (int(nf) // 2) / nf) ** 2) < 2e-3
+
+
 def test_grid_matches_hankel_fzp2mm():
     """4096^2 grid (6.5 samples per outer zone) vs the continuous radial integral."""
     ap = O.Aperture(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096)
