@@ -670,11 +670,15 @@ size_t col_operand_bytes(int M, int64_t chunk_rows) {
   return (size_t)2 * (size_t)KB * (size_t)(2 * M) * sizeof(uint16_t);
 }
 
-size_t col_partial_bytes(int M) {
-  // a chunk gets at most `target` segments (seg_len >= rows / target)
+size_t col_partial_bytes(int M, int64_t chunk_rows) {
+  // a chunk gets at most `target` segments (seg_len >= rows / target), and at
+  // most one per 256 of its K rows (seg_len >= 256; the K extent is the
+  // chunk's rows rounded out to 16 at both ends)
   const ColSchedule c = col_schedule(M, 0, 0);
   const int64_t target = (512 + c.n_rt * c.n_ct - 1) / (c.n_rt * c.n_ct);
-  return (size_t)target * (size_t)M * (size_t)(2 * M) * sizeof(float);
+  const int64_t by_rows = (chunk_rows + 30 + 255) / 256;
+  const int64_t nseg = target < by_rows ? target : by_rows;
+  return (size_t)nseg * (size_t)M * (size_t)(2 * M) * sizeof(float);
 }
 
 namespace {

@@ -150,7 +150,7 @@ hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end,
 // of the product (col_partial_bytes per lane), added in float64 into the ROI.
 size_t col_table_bytes(int M, int64_t Npad);
 size_t col_operand_bytes(int M, int64_t chunk_rows);
-size_t col_partial_bytes(int M);
+size_t col_partial_bytes(int M, int64_t chunk_rows);
 hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st);
 // 2-level phase plates on the split path (fzp_cplx.hip): t = disc - 2 mask
 // (mask = the odd zones), so T = T_disc - 2 T_mask with T_mask from the binary

@@ -380,7 +380,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       if (cplx) p.G_bytes = align256(fzp::split_stripe_bytes(p.inst[0].dev, p.chunk_rows));
       for (const auto &ih : p.inst) {
         p.Tb_bytes = std::max(p.Tb_bytes, align256(fzp::col_operand_bytes(ih.in.M, p.chunk_rows)));
-        p.C_bytes = std::max(p.C_bytes, align256(fzp::col_partial_bytes(ih.in.M)));
+        p.C_bytes = std::max(p.C_bytes, align256(fzp::col_partial_bytes(ih.in.M, p.chunk_rows)));
       }
     }
     for (int l = 0; l < p.lanes_max; ++l) {
