@@ -178,6 +178,25 @@ fzp_status_t fzp_prepare(fzp_plan_t p, void *workspace, void *stream);
  * aperture rows.  Asynchronous on `stream`. */
 fzp_status_t fzp_propagate_roi(fzp_plan_t p, void *workspace, double *roi_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fzp_propagate_roi with the workspace taken from a device array that the
+ * library holds, FZP_STATIC_SCRATCH_BYTES per GPU from the first call on that
+ * GPU until the process ends.  The caller passes the plan and the ROI buffer
+ * (as for fzp_propagate_roi) and nothing else; the call allocates no device
+ * memory and creates no stream or event: every instance runs on `stream` in
+ * one lane (the same bits as fzp_propagate_roi), without kernel timing or the
+ * operand overlap.  The plan's tables are built in the array unless the last
+ * successful call on this GPU used the same plan (the array keeps the last
+ * call's contents).  All calls on one GPU share the array: calls that overlap
+ * in time on one GPU (other threads, other streams) race and give undefined
+ * results.  Errors: FZP_E_INVAL (NULL argument), FZP_E_NOMEM (the plan's
+ * fzp_plan_workspace_size exceeds FZP_STATIC_SCRATCH_BYTES; checked before any
+ * device call: plan with fewer chunk_rows, instances or ROI samples),
+ * FZP_E_DEVICE. */
+#define FZP_STATIC_SCRATCH_BYTES (64u << 20)
+fzp_status_t fzp_propagate_roi_static(fzp_plan_t p, double *roi_dev, void *stream);
+
 /* Contribution of aperture rows row_begin .. row_end-1 only (0 <= begin <= end
  * <= N).  With accumulate = 0 the ROI is overwritten, otherwise added to.  The
  * contributions of a partition of [0, N) into ranges that start on multiples of

@@ -37,10 +37,11 @@ FLAG_BIN_SHALLOW = 4
 FLAG_BIN_PREFETCH = 8
 FLAG_OVERLAP_OPERAND = 16
 FLAG_BIN_DEEP = 32
+STATIC_SCRATCH_BYTES = 64 << 20   # FZP_STATIC_SCRATCH_BYTES
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
-    "fzp_propagate_roi", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
+    "fzp_propagate_roi", "fzp_propagate_roi_static", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
     "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
     "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
@@ -117,6 +118,8 @@ def load_library() -> ctypes.CDLL:
     lib.fzp_prepare.restype = st
     lib.fzp_propagate_roi.argtypes = [P, P, P, P]
     lib.fzp_propagate_roi.restype = st
+    lib.fzp_propagate_roi_static.argtypes = [P, P, P]
+    lib.fzp_propagate_roi_static.restype = st
     lib.fzp_propagate_roi_range.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
     lib.fzp_propagate_roi_range.restype = st
     lib.fzp_propagate_resumable.argtypes = [P, P, P, ctypes.c_char_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -281,6 +284,11 @@ class Plan:
 
     def propagate(self, ws, roi, stream=None):
         _check(self._lib, self._lib.fzp_propagate_roi(self._h, _ptr(ws), _ptr(roi), _stream_handle(stream)))
+
+    def propagate_static(self, roi, stream=None):
+        """fzp_propagate_roi_static: the whole aperture into roi with the library's
+        own device array as the workspace (no device allocation)."""
+        _check(self._lib, self._lib.fzp_propagate_roi_static(self._h, _ptr(roi), _stream_handle(stream)))
 
     def propagate_range(self, ws, roi, row_begin: int, row_end: int, accumulate: bool = False, stream=None):
         _check(self._lib, self._lib.fzp_propagate_roi_range(self._h, _ptr(ws), _ptr(roi), int(row_begin),

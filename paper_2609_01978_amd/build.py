@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfzp.so")
 
-SOURCES = ["fzp_plan.cpp", "fzp_fft.hip", "fzp_gemm.hip", "fzp_cplx.hip", "fzp_metrics.hip", "fzp_mlp.hip"]
+SOURCES = ["fzp_plan.cpp", "fzp_fft.hip", "fzp_gemm.hip", "fzp_cplx.hip", "fzp_metrics.hip", "fzp_mlp.hip",
+           "fzp_static.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

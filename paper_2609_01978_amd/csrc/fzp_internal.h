@@ -77,6 +77,7 @@ struct InstHost {
 };
 
 struct Plan {
+  uint64_t serial = 0;  // unique per plan in the process (fzp_plan)
   fzp_aperture_t ap;
   fzp_options_t opt;
   double dx;
@@ -116,6 +117,15 @@ struct Plan {
 
 // Thread-local text returned by fzp_last_error (fzp_plan.cpp).
 void set_last_error(const std::string &msg);
+
+// One whole propagation of the plan on one lane of `stream` with the workspace
+// at `ws` (fzp_plan.cpp), for fzp_propagate_roi_static: the tables are built
+// there unless `tables_current` says the last plan prepared in it was this one;
+// no stream, event or device memory is created.
+fzp_status_t propagate_fixed_workspace(fzp_plan_t h, char *ws, bool tables_current, double *roi_dev,
+                                       hipStream_t stream);
+uint64_t plan_serial(fzp_plan_t h);
+size_t plan_workspace_bytes(fzp_plan_t h);
 
 // ---- launchers (fzp_fft.hip, fzp_gemm.hip, fzp_metrics.hip) ----
 hipError_t launch_build_tables(const Plan &p, const InstHost &ih, char *ws, hipStream_t st);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <exception>
 #include <fstream>
 #include <sstream>
@@ -146,6 +147,8 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     auto h = new (std::nothrow) fzp_plan_s;
     if (!h) return fail(FZP_E_NOMEM, "fzp_plan: out of host memory");
     Plan &p = h->plan;
+    static std::atomic<uint64_t> next_serial{1};
+    p.serial = next_serial.fetch_add(1, std::memory_order_relaxed);
     p.ap = *ap;
     p.opt = o;
     const int64_t N = ap->N;
@@ -761,6 +764,36 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
 extern "C" fzp_status_t fzp_propagate_roi(fzp_plan_t h, void *workspace, double *roi_dev, void *stream) {
   if (!h) return fail(FZP_E_INVAL, "fzp_propagate_roi: NULL plan");
   return fzp_propagate_roi_range(h, workspace, roi_dev, 0, h->plan.ap.N, 0, stream);
+}
+
+uint64_t fzp::plan_serial(fzp_plan_t h) { return h->plan.serial; }
+
+size_t fzp::plan_workspace_bytes(fzp_plan_t h) { return h->plan.ws_bytes; }
+
+fzp_status_t fzp::propagate_fixed_workspace(fzp_plan_t h, char *ws, bool tables_current, double *roi_dev,
+                                            hipStream_t stream) {
+  Plan &p = h->plan;
+  if (tables_current) {
+    // the tables in ws are this plan's: only the device pointers are re-bound
+    bind_tables(p, ws);
+    p.prepared_ws = ws;
+  } else {
+    const fzp_status_t s = fzp_prepare(h, ws, stream);
+    if (s != FZP_OK) return s;
+  }
+  // one lane on the caller's stream, no profiling events and no auxiliary
+  // stream: nothing is created (lanes give the same bits as one lane)
+  const int32_t lanes = p.lanes;
+  const bool prof = p.profile;
+  const int32_t flags = p.opt.flags;
+  p.lanes = 1;
+  p.profile = false;
+  p.opt.flags &= ~FZP_FLAG_OVERLAP_OPERAND;
+  const fzp_status_t s = fzp_propagate_roi_range(h, ws, roi_dev, 0, p.ap.N, 0, stream);
+  p.lanes = lanes;
+  p.profile = prof;
+  p.opt.flags = flags;
+  return s;
 }
 
 namespace {

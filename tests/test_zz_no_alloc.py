@@ -1,0 +1,73 @@
+"""fzp_propagate_roi_static, the propagation for callers that cannot allocate:
+its workspace is the library's own device array.  Through the C ABI its ROI
+must equal fzp_propagate_roi's on the same plan (the same kernels and chunk
+schedule on one lane), on consecutive calls that reuse the array, the later
+ones with smaller inputs; plans too large for the array are refused before any
+device call."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2609_01978_amd as P
+from paper_2609_01978_amd import _lib as L
+from fzp_inputs import crease_draws
+
+LAM0 = 632.8e-9
+
+
+def announce(msg):
+    print(f"[no-alloc] {msg}", flush=True)
+
+
+def plans(path):
+    """A larger plan (N = 4096, ROIs 256 and 128, one creased) and a smaller
+    one (N = 2048, one ROI of 64), both within FZP_STATIC_SCRATCH_BYTES."""
+    big = P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096),
+                 [dict(lam=LAM0, M=256), dict(lam=560e-9, M=128, creases=crease_draws(7, 2e-3, LAM0, 8))],
+                 path=path, chunk_rows=512)
+    small = P.Plan(dict(D=1e-3, f0=5e-3, lambda0=LAM0, N=2048), [dict(lam=700e-9, M=64, x0=1e-6)],
+                   path=path, chunk_rows=512)
+    for p in (big, small):
+        assert p.workspace_size <= L.STATIC_SCRATCH_BYTES
+    return big, small
+
+
+def test_oversized_plan_is_refused_before_any_device_call():
+    lib = P.load_library()
+    plan = P.Plan(dict(D=20e-3, f0=100e-3, lambda0=LAM0, N=32768), [dict(lam=LAM0, M=1024)])
+    assert plan.workspace_size > L.STATIC_SCRATCH_BYTES
+    st = lib.fzp_propagate_roi_static(plan._h, ctypes.c_void_p(1 << 20), None)
+    assert st == L.FZP_E_NOMEM
+    assert b"FZP_STATIC_SCRATCH_BYTES" in lib.fzp_last_error()
+    assert lib.fzp_propagate_roi_static(None, ctypes.c_void_p(1 << 20), None) == L.FZP_E_INVAL
+    assert lib.fzp_propagate_roi_static(plan._h, None, None) == L.FZP_E_INVAL
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("path,tol", [("fp64", 1e-9), ("split", 1e-4)])
+def test_static_workspace_matches_caller_workspace(path, tol):
+    torch = pytest.importorskip("torch")
+    big, small = plans(path)
+    # two calls in a row on the shared array, the second with the smaller plan,
+    # then the larger plan again (its tables rebuilt over the smaller plan's)
+    # and once more (its tables reused)
+    for rep, plan in enumerate((big, small, big, big)):
+        roi_s = torch.full((2 * plan.roi_elements,), float("nan"), dtype=torch.float64, device="cuda")
+        announce(f"{path} call {rep}: N-plan workspace {plan.workspace_size} bytes, ROIs {plan.Ms}")
+        plan.propagate_static(roi_s)
+        ws, roi_w = plan.alloc()
+        plan.propagate(ws, roi_w)
+        torch.cuda.synchronize()
+        for k in range(plan.n_instances):
+            a = plan.roi_view(roi_s, k).cpu().numpy()
+            b = plan.roi_view(roi_w, k).cpu().numpy()
+            assert np.isfinite(a).all()
+            if path == "fp64":
+                e = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            else:
+                ia, ib = np.abs(a) ** 2, np.abs(b) ** 2
+                e = float(np.linalg.norm(ia - ib) / np.linalg.norm(ib))
+            announce(f"  instance {k}: rel-L2 {e:.2e}, bit-identical {np.array_equal(a, b)}")
+            assert e <= tol, (rep, k, e)
+        del ws, roi_w
