@@ -13,11 +13,13 @@ split result is valid only when its ROI intensity is within rel-L2 1e-4 of the
 float64 path's.  Inputs are synthetic and analytic (the zone plate itself).
 
 Besides the headline it reports, on the same GPU: the 64-instance creased
-batch of the 20 mm element (graph-launched, autotuned), the 0.1 m 4- and
-2-level phase plates (``ml100mm``, ``ml100mm_l2``), the CPU oracle on a
-sample of the workload, and on
-request the grid-convergence sweep of the accuracy study (``--convergence``)
-and the learned surrogate (``--surrogate``).
+batch of the 20 mm element (graph-launched, autotuned, with the roofline of
+its complex-stripe GEMM), the 0.1 m 4- and 2-level phase plates
+(``ml100mm``, ``ml100mm_l2``), the 2 mm and 20 mm elements on both paths
+(``configs``), a reduced run of the learned surrogate (``surrogate``; the
+full 20k-solve run with ``--surrogate``), the CPU oracle on a sample of the
+workload (on every core this process may use), and on request the
+grid-convergence sweep of the accuracy study (``--convergence``).
 
 Prints exactly one JSON line.
 """
@@ -36,10 +38,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fzp1m", choices=["fzp2mm", "fzp20mm", "fzp1m"])
-    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the float64 comparison path")
+    ap.add_argument("--fp64-steps", type=int, default=5, help="timed steps of the float64 comparison path")
+    ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed steps of the float64 comparison path")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=256, help="aperture rows in the CPU oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="aperture rows in the CPU oracle sample (0: sized for about 15 s of oracle work)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 2 mm and 20 mm elements (both paths, full aperture)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the reduced surrogate run (4096 + 512 + 512 CZT solves, 30 epochs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch of the 20 mm element")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
@@ -49,7 +57,8 @@ def parse():
                          "532 nm, N = 1024 .. 28672) on both paths")
     ap.add_argument("--multilevel-steps", type=int, default=2)
     ap.add_argument("--surrogate", action="store_true",
-                    help="also train and evaluate the learned surrogate (20k + 1k CZT solves)")
+                    help="train and evaluate the learned surrogate at full size (20k + 1k CZT solves) instead "
+                         "of the reduced run")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
@@ -116,21 +125,54 @@ def bluestein_blocks(N: int, B: int) -> int:
     return int(np.sum((length + B - 1) // B))
 
 
+def host_cpu():
+    """(CPU model, threads this process may use): the affinity mask, capped by
+    OMP_NUM_THREADS when the host sets it (the box's share of its cores)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return model, max(n, 1)
+
+
 def cpu_baseline(w, rows_n: int):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
-    `rows_n` aperture rows through the middle of the aperture, Bluestein form."""
+    `rows_n` aperture rows through the middle of the aperture, Bluestein form,
+    with scipy.fft's workers (and the BLAS threads) on every core this process
+    may use.  rows_n = 0 sizes the sample for about 15 s from a 64-row probe."""
     import numpy as np
+    from scipy import fft as sfft
     from oracle import fzp_oracle as O
+    model, cores = host_cpu()
     a = O.Aperture(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
     i = O.Instance(lam=w["lambda0"], M=w["M"])
     N = a.N
-    j0 = N // 2 - rows_n // 2
-    t = time.perf_counter()
-    O.propagate(a, i, method="bluestein", rows=(j0, j0 + rows_n), stripe=32)
-    dt = time.perf_counter() - t
-    return dict(value=rows_n * N / dt / 1e9, unit="Gsamples/s", cores=1, kind="oracle",
+    stripe = 64
+
+    def timed(rows):
+        j0 = N // 2 - rows // 2
+        t = time.perf_counter()
+        with sfft.set_workers(cores):
+            O.propagate(a, i, method="bluestein", rows=(j0, j0 + rows), stripe=stripe)
+        return time.perf_counter() - t
+
+    if rows_n <= 0:
+        probe = timed(stripe)
+        rows_n = int(min(max(15.0 / max(probe, 1e-3) * stripe, stripe), N)) // stripe * stripe
+    dt = timed(rows_n)
+    return dict(value=rows_n * N / dt / 1e9, unit="Gsamples/s", cores=cores, cpu_model=model, kind="oracle",
                 sample=f"{rows_n} aperture rows x {N} columns through the centre of the {w['D']} m aperture "
-                       f"(float64 Bluestein form, scipy.fft single worker), {dt:.1f} s")
+                       f"(float64 Bluestein form, scipy.fft with {cores} workers, NumPy's elementwise steps on one "
+                       f"thread), {dt:.1f} s")
 
 
 def run_batch(args, dev):
@@ -169,6 +211,32 @@ def run_batch(args, dev):
         del g, ws, roi
         torch.cuda.empty_cache()
     errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(I["split"], I["fp64"])]
+    # Roofline of the batch's dominant kernel, the complex-stripe row GEMM
+    # (k_row_pass_split_cplx): 24 M flops per disc sample of a creased instance
+    # (three split products of a complex product).  One more propagation on a
+    # one-lane plan with HIP events around each launch, so that no interval
+    # holds another lane's kernels.
+    plan = P.Plan(ap, insts, path="split", lanes=1)
+    ws, roi = plan.alloc(dev)
+    plan.propagate(ws, roi)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read(reset=True)
+    plan.propagate(ws, roi)
+    torch.cuda.synchronize()
+    pr = plan.profile_read(reset=True)
+    disc = float(plan.info()["disc_samples"])
+    flops = sum(24.0 * inst["M"] * disc for inst in insts)
+    ach = flops / (pr["row_ms"] * 1e-3) / 1e12
+    res["split"]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                                    frac=round(ach / PEAK_BF16_TFLOPS, 4), kernel="k_row_pass_split_cplx",
+                                    launches=pr["row_launches"], row_gemm_ms=round(pr["row_ms"], 3),
+                                    stripe_ms=round(pr["mask_ms"], 3), col_pass_ms=round(pr["col_ms"], 3),
+                                    flops_per_batch=flops,
+                                    work="24 M flops per disc sample of each creased instance (one lane, "
+                                         "default K segments)")
+    del ws, roi, plan
+    torch.cuda.empty_cache()
     return {"workload": "64 instances: D=20 mm f/5 N=32768^2, lambda 500-800 nm x 4 crease maps (8 creases), "
                         "M in {256,512,1024}", "instances": len(insts), "steps": args.batch_steps,
             "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
@@ -242,6 +310,47 @@ def run_multilevel(args, dev, levels=None):
             "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
             "de_ladder_sinc2": round((math.sin(x) / x) ** 2 * lobe, 6),
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
+
+
+def run_configs(dev, steps: int = 3):
+    """The 2 mm (N = 4096, M = 256) and 20 mm (N = 32768, M = 1024) elements on
+    both paths: whole-aperture propagation plus metrics per step, after one
+    warm-up step; split intensity against the FP64 path's."""
+    import numpy as np
+    import torch
+    import paper_2609_01978_amd as P
+    from fzp_inputs import workload
+    out = {}
+    for name in ("fzp2mm", "fzp20mm"):
+        w = workload(name)
+        ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+        inst = dict(lam=w["lambda0"], M=w["M"])
+        samples = float(w["N"]) ** 2
+        res, I = {}, {}
+        for path in ("split", "fp64"):
+            plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"] if path == "split" else 0)
+            ws, roi = plan.alloc(dev)
+            plan.propagate(ws, roi)
+            plan.metrics(ws, roi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.propagate(ws, roi)
+                m = plan.metrics(ws, roi)[0]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
+            res[path] = {"gsamples_s": round(samples / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
+                         "fwhm_x": m["fwhm_x"], "de": m["de"]}
+            del ws, roi, plan
+            torch.cuda.empty_cache()
+        e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
+        log(f"{name}: split {res['split']['ms_per_step']} ms, fp64 {res['fp64']['ms_per_step']} ms, rel-L2 {e:.2e}")
+        out[name] = {"workload": f"binary FZP D={w['D']} m f/5 lambda=632.8 nm, N={w['N']}^2, ROI {w['M']}^2",
+                     "steps": steps, "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
+                     "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
+                     "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
+    return out
 
 
 # Closed forms of the ideal Airy pattern (aberration-free circular pupil):
@@ -362,7 +471,7 @@ def main():
     split = run_path("split", args.steps, args.warmup)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_path("fp64", args.fp64_steps, 0)
+        fp64 = run_path("fp64", args.fp64_steps, args.fp64_warmup)
 
     value = samples / (split["ms"] * 1e-3) / 1e9
     rel = None
@@ -446,12 +555,18 @@ def main():
     if not args.no_multilevel:
         out["ml100mm"] = run_multilevel(args, dev)
         out["ml100mm_l2"] = run_multilevel(args, dev, levels=2)
+    if not args.no_configs:
+        out["configs"] = run_configs(dev)
     if args.convergence:
         out["convergence"] = run_convergence(dev)
-    if args.surrogate:
+    if args.surrogate or not args.no_surrogate:
         from paper_2609_01978_amd import surrogate as SG
         sw = workload("surrogate")
-        out["surrogate"] = SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
+        if args.surrogate:
+            out["surrogate"] = SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
+        else:
+            out["surrogate"] = SG.run(sw, 4096, 512, 512, 30, log=log)
+            out["surrogate"]["reduced"] = "4096 training, 512 validation, 512 test solves, 30 epochs"
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
