@@ -74,6 +74,20 @@ typedef int32_t fzp_status_t;
                                      2-level phase plate), 256 (creased amplitude plate, or
                                      crease-free 4-level phase plate), 128 (other phase
                                      plates); fzp_plan_info reports the choice */
+#define FZP_PATH_SA_CZT 3         /* non-paraxial variant, the semi-analytical chirp-z transform
+                                     (Sec. 3.6, Fig. 5): the amplitude plate with the sag-corrected
+                                     radii of Eq. 3 centred in a zero-padded grid of Np >= 1.5 N
+                                     samples per side; its 2-D FFT times exp(i h(K) z), the
+                                     remainder of the exact transfer function exp(i k_z z),
+                                     k_z = sqrt(k0^2 - K^2), after the quadratic
+                                     c k_max + d K^2 / k_max fitted at K = 0 and K = k_max = 2 k0 / 3
+                                     (Sec. 3.4, Fig. 3), back to space; then the quadratic part as a
+                                     chirp-z zoom onto the ROI with Z = 4 pi |d| z / k_max in place
+                                     of lambda z, prefactor e^{i k0 z} / (i Z) e^{i pi (x'^2+y'^2)/Z}.
+                                     Float64 throughout; the padded field (Np^2 x 16 bytes) is in the
+                                     workspace.  Whole apertures only: a partial row range is
+                                     FZP_E_UNSUPPORTED.  Amplitude plates (levels = 0), creases
+                                     allowed, one lane. */
 
 /* Plan flags. */
 #define FZP_FLAG_ALLOW_UNDERSAMPLED 1 /* skip the Eq. 6 check (tests on tiny grids) */
@@ -86,6 +100,9 @@ typedef int32_t fzp_status_t;
 #define FZP_FLAG_BIN_PREFETCH 8       /* variant 3: variant 2 reading the next stage's first
                                          operand fragments one stage early */
 #define FZP_FLAG_BIN_DEEP 32          /* variant 2: 512-row tile with an 8-stage LDS pipeline */
+#define FZP_FLAG_PARAXIAL_RADII 64    /* FZP_PATH_SA_CZT: the paraxial radii of Eq. 4 (r_n^2 = n
+                                         lambda0 f0) instead of Eq. 3, e.g. to compare with the
+                                         Fresnel paths */
 #define FZP_FLAG_OVERLAP_OPERAND 16   /* split path: make each chunk's stripe operand on an internal
                                          auxiliary stream one chunk ahead of its GEMM (two operand
                                          buffers); not under stream capture: fzp_graph_create,
@@ -97,7 +114,7 @@ typedef struct {
   double f0;         /* design focal length */
   double lambda0;    /* design wavelength (zone radii r_n^2 = n lambda0 f0) */
   double pitch;      /* sample pitch; 0 means D / N */
-  int64_t N;         /* samples per side, 1 .. 2^21 */
+  int64_t N;         /* samples per side, 1 .. 2^21 (FZP_PATH_SA_CZT: padded grid up to 2^20) */
   int32_t centre_open; /* amplitude plates: 0 central zone opaque (odd zones open), 1 central
                           zone open; must be 0 for phase plates */
   int32_t levels;      /* 0: binary amplitude plate (Sec. 2.2).  2 .. 64: L-level phase plate
@@ -139,6 +156,8 @@ typedef struct {
   int32_t lanes;        /* instances propagated concurrently, each lane on its own
                            internal stream with its own stripe buffers (the workspace
                            grows by one set of stripe buffers per lane); 0 = 1, at most 8 */
+  double pad;           /* FZP_PATH_SA_CZT: padded grid Np = the smallest 2^a 3^b 5^c >= pad N
+                           with the parity of N; 0 = 1.5 (the paper's pad), else 1 .. 8 */
 } fzp_options_t;
 
 /* Main-lobe metrics of one instance (shared metric extractor, Sec. 3.3 stage 4
@@ -239,6 +258,21 @@ fzp_status_t fzp_metrics(fzp_plan_t p, void *workspace, const double *roi_dev,
 fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64_t *chunk_rows,
                            int32_t *stripe_rows, int32_t *path, int64_t *disc_samples,
                            double *kappa);
+
+/* Geometry of a plan.  zones_exact is the real root n of Eq. 3 at r = D/2,
+ * (lambda0^2/4) n^2 + lambda0 f0 n = (D/2)^2, and total_zones its floor (the zone
+ * count of Fig. 2 stage 2, reported for every path).  For FZP_PATH_SA_CZT:
+ * padded_n = Np, fft_n1 x fft_n2 = Np (the two LDS transform lengths of each
+ * axis) and zoom_distance = Z / lambda of instance k (the distance of the
+ * zoom's Fresnel-type transform); 0 otherwise.  Errors: FZP_E_INVAL. */
+typedef struct {
+  double zones_exact;
+  int64_t total_zones;
+  int64_t padded_n;
+  int32_t fft_n1, fft_n2;
+  double zoom_distance;
+} fzp_geometry_t;
+fzp_status_t fzp_plan_geometry(fzp_plan_t p, int32_t k, fzp_geometry_t *out);
 
 /* Kernel timing.  While enabled, every kernel launch of
  * fzp_propagate_roi(_range) - row pass, column pass, and (split path) the

@@ -101,9 +101,12 @@ def zone_mask_eq3(ap: F.Aperture, j0: int = 0, j1: Optional[int] = None) -> np.n
     return F.disc_mask(ap, j0, j1) & odd
 
 
-def padded_aperture(ap: F.Aperture, radii: str = "eq3", pad: float = 1.5) -> np.ndarray:
+def padded_aperture(ap: F.Aperture, radii: str = "eq3", pad: float = 1.5,
+                    inst: Optional[F.Instance] = None) -> np.ndarray:
     """The mask (radii 'eq3', 'paraxial' or 'disc' for a clear aperture) centred
-    in the zero-padded Np x Np grid (complex128)."""
+    in the zero-padded Np x Np grid (complex128), times the membrane phase
+    screen exp(2 pi i h / lambda) of the instance's creases when it has any (the
+    thin-screen deformation model of the paraxial oracle)."""
     Np = pad_size(ap.N, pad)
     off = (Np - ap.N) // 2
     if radii == "eq3":
@@ -114,8 +117,12 @@ def padded_aperture(ap: F.Aperture, radii: str = "eq3", pad: float = 1.5) -> np.
         m = F.disc_mask(ap)
     else:
         raise ValueError(radii)
+    t = m.astype(np.complex128)
+    if inst is not None and inst.creases is not None and len(inst.creases):
+        x = F.aperture_coords(ap)
+        t = t * np.exp(2j * np.pi * F.crease_height(x[None, :], x[:, None], inst.creases) / inst.lam)
     U0 = np.zeros((Np, Np), dtype=np.complex128)
-    U0[off:off + ap.N, off:off + ap.N] = m
+    U0[off:off + ap.N, off:off + ap.N] = t
     return U0
 
 
@@ -151,7 +158,7 @@ def sa_czt(ap: F.Aperture, inst: F.Instance, radii: str = "eq3", pad: float = 1.
     r = F.resolve(ap, inst)
     lam, z = r["lam"], r["z"]
     k0, kmax, c, d = fit_constants(lam, k_fit)
-    U0 = padded_aperture(ap, radii, pad)
+    U0 = padded_aperture(ap, radii, pad, inst)
     U1 = angular_spectrum_step(U0, ap.dx, lam, z, k_fit)
     Z = 4.0 * np.pi * abs(d) * z / kmax
     xq = F.roi_coords(inst.M, inst.x0, r["dx_out"])

@@ -31,17 +31,19 @@ STATUS_NAMES = {0: "FZP_OK", -1: "FZP_E_INVAL", -2: "FZP_E_SAMPLING", -3: "FZP_E
 PATH_FP64_BLUESTEIN = 0
 PATH_SPLIT_BF16 = 1
 PATH_AUTO = 2
+PATH_SA_CZT = 3
 FLAG_ALLOW_UNDERSAMPLED = 1
 FLAG_BIN_TILE_256 = 2
 FLAG_BIN_SHALLOW = 4
 FLAG_BIN_PREFETCH = 8
 FLAG_OVERLAP_OPERAND = 16
 FLAG_BIN_DEEP = 32
+FLAG_PARAXIAL_RADII = 64
 STATIC_SCRATCH_BYTES = 64 << 20   # FZP_STATIC_SCRATCH_BYTES
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
-    "fzp_propagate_roi", "fzp_propagate_roi_static", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_destroy",
+    "fzp_propagate_roi", "fzp_propagate_roi_static", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_plan_geometry", "fzp_destroy",
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
     "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
     "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
@@ -74,7 +76,16 @@ class Instance(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("stripe_rows", ctypes.c_int32), ("chunk_rows", ctypes.c_int64),
-                ("workspace_limit", ctypes.c_uint64), ("flags", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+                ("workspace_limit", ctypes.c_uint64), ("flags", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("pad", ctypes.c_double)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("zones_exact", ctypes.c_double), ("total_zones", ctypes.c_int64), ("padded_n", ctypes.c_int64),
+                ("fft_n1", ctypes.c_int32), ("fft_n2", ctypes.c_int32), ("zoom_distance", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class Metrics(ctypes.Structure):
@@ -132,6 +143,8 @@ def load_library() -> ctypes.CDLL:
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_double)]
     lib.fzp_plan_info.restype = st
+    lib.fzp_plan_geometry.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Geometry)]
+    lib.fzp_plan_geometry.restype = st
     lib.fzp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.fzp_profile_enable.restype = st
     lib.fzp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -196,7 +209,8 @@ class Plan:
 
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
                  chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
-                 lanes: int = 0, variant: int = 4, overlap_operand: bool = False):
+                 lanes: int = 0, variant: int = 4, overlap_operand: bool = False, pad: float = 0.0,
+                 paraxial_radii: bool = False):
         lib = load_library()
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
@@ -216,13 +230,14 @@ class Plan:
             arr[k] = Instance(lambda_=inst["lam"], z=inst.get("z", 0.0), x0=inst.get("x0", 0.0),
                               y0=inst.get("y0", 0.0), half_width=inst.get("half_width", 0.0), M=int(inst["M"]),
                               n_creases=ncr, creases=ctypes.cast(cbuf, ctypes.POINTER(Crease)))
-        p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16, "auto": PATH_AUTO}[path] \
+        p = {"fp64": PATH_FP64_BLUESTEIN, "split": PATH_SPLIT_BF16, "auto": PATH_AUTO, "sa": PATH_SA_CZT}[path] \
             if isinstance(path, str) else int(path)
         opt = Options(path=p, stripe_rows=stripe_rows, chunk_rows=chunk_rows, workspace_limit=workspace_limit,
                       flags=(FLAG_ALLOW_UNDERSAMPLED if allow_undersampled else 0)
                       | {0: FLAG_BIN_SHALLOW, 1: FLAG_BIN_TILE_256, 2: FLAG_BIN_DEEP,
                          3: FLAG_BIN_PREFETCH, 4: 0}[variant]
-                      | (FLAG_OVERLAP_OPERAND if overlap_operand else 0), lanes=int(lanes))
+                      | (FLAG_OVERLAP_OPERAND if overlap_operand else 0)
+                      | (FLAG_PARAXIAL_RADII if paraxial_radii else 0), lanes=int(lanes), pad=float(pad))
         h = ctypes.c_void_p()
         _check(lib, lib.fzp_plan(ctypes.byref(ap), arr, n, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -262,6 +277,13 @@ class Plan:
                                                   ctypes.byref(kap)))
         return dict(fft_len=a.value, block=b.value, chunk_rows=c.value, stripe_rows=s.value, path=pth.value,
                     disc_samples=ds.value, kappa=kap.value)
+
+    def geometry(self, k: int = 0) -> dict:
+        """fzp_plan_geometry: the Eq. 3 zone count and, on the non-paraxial path,
+        the padded grid, its FFT factors and the zoom distance of instance k."""
+        g = Geometry()
+        _check(self._lib, self._lib.fzp_plan_geometry(self._h, int(k), ctypes.byref(g)))
+        return g.as_dict()
 
     # -- device buffers (torch) ---------------------------------------------
     def alloc(self, device="cuda"):

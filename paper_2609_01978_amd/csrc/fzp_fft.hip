@@ -327,6 +327,42 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_col_pass(InstDev d, int64_t 
   }
 }
 
+// Row pass over stored rows (the CZT zoom of the non-paraxial variant): row
+// `row` of a field of d.N x d.N samples (its chirp is part of the kernel), all
+// d.N samples, into T[row - row_begin][q].
+struct StoredRow {
+  static constexpr bool kBlock = true;
+  const double2 *row;
+  __device__ __forceinline__ void block(int64_t i0, int64_t cnt, double2 v[16]) const {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t n = t + 256 * r;
+      v[r] = n < cnt ? row[i0 + n] : make_double2(0.0, 0.0);
+    }
+  }
+};
+
+template <int NQ>
+__global__ __launch_bounds__(kFftThreads, 2) void k_row_pass_stored(InstDev d, const double2 *__restrict__ U,
+                                                                    int64_t row_begin, int64_t row_end,
+                                                                    double2 *__restrict__ T) {
+  __shared__ double2 s_lds[kLdsN];
+  const int t = threadIdx.x;
+  const Tw tw = fft_twiddles();
+  const int M = d.M;
+  for (int64_t row = row_begin + blockIdx.x; row < row_end; row += gridDim.x) {
+    double2 acc[NQ];
+    bluestein_line<NQ>(d, d.Hx, d.sx, 0, d.N, s_lds, tw, acc, StoredRow{U + row * d.N});
+    double2 *Trow = T + (row - row_begin) * (int64_t)M;
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) {
+      const int q = t + 256 * r;
+      if (r * 256 < M && q < M) Trow[q] = cmul(acc[r], d.Qx[q]);
+    }
+  }
+}
+
 int grid_for(int64_t work, int per_cu) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -375,6 +411,26 @@ hipError_t launch_row_pass_fp64(const InstDev &d, int64_t row_begin, int64_t row
     FZP_ROW(8)
   }
 #undef FZP_ROW
+  return hipGetLastError();
+}
+
+hipError_t launch_row_pass_stored(const InstDev &d, const double2 *U, int64_t row_begin, int64_t row_end,
+                                  double2 *T, hipStream_t st) {
+  const int64_t rows = row_end - row_begin;
+  if (rows <= 0) return hipSuccess;
+  const int grid = grid_for(rows, 2);
+#define FZP_ROWS(NQ) \
+  hipLaunchKernelGGL((k_row_pass_stored<NQ>), dim3(grid), dim3(kFftThreads), 0, st, d, U, row_begin, row_end, T);
+  if (d.M <= 256) {
+    FZP_ROWS(1)
+  } else if (d.M <= 512) {
+    FZP_ROWS(2)
+  } else if (d.M <= 1024) {
+    FZP_ROWS(4)
+  } else {
+    FZP_ROWS(8)
+  }
+#undef FZP_ROWS
   return hipGetLastError();
 }
 

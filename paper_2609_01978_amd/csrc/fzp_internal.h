@@ -65,6 +65,30 @@ struct InstDev {
   double kappa_l;          // phase plates: kappa * (L / 2); level = floor(K kappa_l) mod L
 };
 
+// Non-paraxial variant (fzp_sa.hip): the padded grid, its two FFT factors
+// with their radix sequences, the aperture rule and the transfer function.
+constexpr int kSaMaxStages = 12;
+struct SaDev {
+  int64_t Np;              // padded samples per side, Np = n1 n2
+  int64_t N, off;          // aperture samples per side; its first sample in the padded grid
+  int32_t n1, n2;          // LDS transform lengths (<= 1024)
+  int32_t nst1, nst2;      // radix stages of n1 and n2
+  int32_t rad1[kSaMaxStages], rad2[kSaMaxStages];
+  int32_t radii_eq3;       // 1: sag-corrected radii (Eq. 3), 0: paraxial radii (Eq. 4)
+  int32_t centre_open, n_creases;
+  double kmax_disc;        // K_max of the aperture disc (exact integer)
+  double c1, c2;           // Eq. 3 zone index floor(c2 q / (sqrt(1 + q) + 1)), q = K c1
+  double kappa;            // Eq. 4 zone index floor(K kappa)
+  double dx;
+  double inv_lam, inv_lam2;  // 1 / lambda and its square
+  double coef;             // d lambda / k_fit (the fitted quadratic's K^2 term, per rho^2)
+  double z;                // propagation distance
+  double inv_L2;           // 1 / (Np dx)^2: rho^2 per squared frequency index
+  double norm;             // 1 / Np^2 (the unnormalised inverse transform)
+  const CreaseDev *cr;
+  const double2 *twNp, *tw1, *tw2;  // W_Np^m, W_n1^k, W_n2^k
+};
+
 struct InstHost {
   fzp_instance_t in;  // creases pointer cleared
   std::vector<fzp_crease_t> creases;
@@ -72,6 +96,8 @@ struct InstHost {
   InstDev dev;
   size_t off_Hx, off_Hy, off_Dt, off_Qx, off_Qy, off_cr, off_A, off_By, off_S;
   int64_t roi_off;     // complex elements
+  SaDev sa;            // FZP_PATH_SA_CZT: the padded-grid pass parameters
+  double Z = 0.0;      // FZP_PATH_SA_CZT: the zoom's lambda z
   int32_t table_owner; // instance whose split table this one shares (itself if none)
   int32_t col_owner;   // instance whose column table (B_y) this one shares (itself if none)
 };
@@ -102,6 +128,8 @@ struct Plan {
   std::vector<hipStream_t> aux_st;  // split path: stripe-operand stream of each lane
   std::vector<hipEvent_t> aux_ev;   // 5 per lane: fork, operand ready x2, GEMM done x2
   bool capturing = false;           // inside fzp_graph_create's stream capture
+  // FZP_PATH_SA_CZT: padded field U1 (Np^2 complex) and the twiddle tables
+  size_t off_U1 = 0, off_twNp = 0, off_tw1 = 0, off_tw2 = 0;
   size_t off_scratch, scratch_bytes;
   size_t ws_bytes;
   const void *prepared_ws = nullptr;
@@ -171,6 +199,14 @@ size_t prefix_table_bytes(int M, int64_t Npad);
 hipError_t launch_build_prefix_table(const InstDev &d, double2 *S, hipStream_t st);
 hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
                                  int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st);
+// Non-paraxial variant (fzp_sa.hip, fzp_fft.hip): twiddle tables, the
+// propagated padded field U1 by seven passes of LDS FFTs, and the CZT zoom's
+// row pass over U1's rows (the column pass is launch_col_pass).
+hipError_t launch_sa_twiddles(const SaDev &a, double2 *twNp, double2 *tw1, double2 *tw2, hipStream_t st);
+hipError_t launch_sa_field(const SaDev &a, double2 *U1, hipStream_t st);
+hipError_t init_sa_attributes();
+hipError_t launch_row_pass_stored(const InstDev &d, const double2 *U1, int64_t row_begin, int64_t row_end,
+                                  double2 *T, hipStream_t st);
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,
                           fzp_metrics_t *dev_out, hipStream_t st);
 size_t metrics_scratch_bytes(int32_t M);

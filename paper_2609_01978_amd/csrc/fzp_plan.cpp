@@ -102,6 +102,91 @@ void set_variant(fzp::Plan &p, int32_t v) {
 using fzp::InstDev;
 using fzp::InstHost;
 using fzp::Plan;
+using fzp::SaDev;
+
+namespace {
+
+bool smooth235(int64_t m) {
+  for (int64_t f : {2, 3, 5})
+    while (m % f == 0) m /= f;
+  return m == 1;
+}
+
+// Radix stages of an LDS transform length (radices 8, 4, 2, 3, 5).
+bool radices_of(int n, int32_t *r, int32_t &nst) {
+  nst = 0;
+  for (int f : {8, 4, 2, 3, 5})
+    while (n % f == 0) {
+      if (nst == fzp::kSaMaxStages) return false;
+      r[nst++] = f;
+      n /= f;
+    }
+  return n == 1;
+}
+
+// Non-paraxial variant (Sec. 3.6, Fig. 5): padded size Np = the smallest
+// 2^a 3^b 5^c >= pad N with the parity of N (the aperture then sits on the
+// padded grid's own sample positions), its factors n1 <= n2 <= 1024, and per
+// instance the transfer-function constants (k_max = 2 k0 / 3, the two-point fit
+// c = k0 / k_max, d = (sqrt(k0^2 - k_max^2) - k0) / k_max) and the zoom as a
+// chirp-z pass with Z = 4 pi |d| z / k_max in place of lambda z.
+fzp_status_t plan_sa(Plan &p, double pad) {
+  const int64_t N = p.ap.N;
+  int64_t Np = (int64_t)std::ceil(pad * (double)N);
+  while (!(smooth235(Np) && (Np - N) % 2 == 0)) ++Np;
+  int64_t n1 = 0;
+  for (int64_t c = (int64_t)std::sqrt((double)Np) + 1; c >= 1; --c)
+    if (Np % c == 0 && c * c <= Np && Np / c <= 1024) {
+      n1 = c;
+      break;
+    }
+  if (n1 == 0 || Np > (int64_t(1) << 20))
+    return fail(FZP_E_UNSUPPORTED, "fzp_plan: padded grid of " + std::to_string(Np) + " samples per side is too large");
+  const int64_t n2 = Np / n1;
+  SaDev a;
+  std::memset(&a, 0, sizeof(a));
+  a.Np = Np;
+  a.N = N;
+  a.off = (Np - N) / 2;
+  a.n1 = (int32_t)n1;
+  a.n2 = (int32_t)n2;
+  if (!radices_of(a.n1, a.rad1, a.nst1) || !radices_of(a.n2, a.rad2, a.nst2))
+    return fail(FZP_E_UNSUPPORTED, "fzp_plan: padded grid does not factor into radices 2, 3, 5");
+  a.radii_eq3 = (p.opt.flags & FZP_FLAG_PARAXIAL_RADII) ? 0 : 1;
+  a.centre_open = p.ap.centre_open;
+  a.kmax_disc = (double)p.kmax;
+  a.c1 = p.dx * p.dx / (4.0 * p.ap.f0 * p.ap.f0);
+  a.c2 = 2.0 * p.ap.f0 / p.ap.lambda0;
+  a.kappa = p.kappa;
+  a.dx = p.dx;
+  a.inv_L2 = 1.0 / ((double)Np * p.dx * (double)Np * p.dx);
+  a.norm = 1.0 / ((double)Np * (double)Np);
+  const double k_fit = 2.0 / 3.0;
+  for (auto &ih : p.inst) {
+    SaDev s = a;
+    const double lam = ih.lam, z = ih.z;
+    const double k0 = 2.0 * M_PI / lam;
+    const double kmx = k_fit * k0;
+    const double d = (std::sqrt(k0 * k0 - kmx * kmx) - k0) / kmx;
+    s.n_creases = ih.in.n_creases;
+    s.inv_lam = 1.0 / lam;
+    s.inv_lam2 = s.inv_lam * s.inv_lam;
+    s.coef = d * lam / k_fit;
+    s.z = z;
+    ih.sa = s;
+    ih.Z = 4.0 * M_PI * std::fabs(d) * z / kmx;
+    // the zoom: a chirp-z pass over the Np x Np field with lambda z -> Z
+    InstDev &dv = ih.dev;
+    dv.N = Np;
+    dv.alpha = p.dx * ih.dx_out / ih.Z;
+    dv.beta = p.dx * p.dx / ih.Z;
+    dv.scale = p.dx * p.dx / ih.Z;
+    dv.inv2lz = 1.0 / (2.0 * ih.Z);
+  }
+  return FZP_OK;
+}
+
+}  // namespace
 
 extern "C" const char *fzp_last_error(void) { return g_err.c_str(); }
 
@@ -114,8 +199,13 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     *out = nullptr;
     fzp_options_t o{};
     if (opt) o = *opt;
-    if (o.path != FZP_PATH_FP64_BLUESTEIN && o.path != FZP_PATH_SPLIT_BF16 && o.path != FZP_PATH_AUTO)
+    if (o.path != FZP_PATH_FP64_BLUESTEIN && o.path != FZP_PATH_SPLIT_BF16 && o.path != FZP_PATH_AUTO &&
+        o.path != FZP_PATH_SA_CZT)
       return fail(FZP_E_INVAL, "fzp_plan: unknown path");
+    if (!(std::isfinite(o.pad) && (o.pad == 0.0 || (o.pad >= 1.0 && o.pad <= 8.0))))
+      return fail(FZP_E_INVAL, "fzp_plan: pad must be 0 (1.5) or in 1 .. 8");
+    if (o.path == FZP_PATH_SA_CZT && ap->levels != 0)
+      return fail(FZP_E_UNSUPPORTED, "fzp_plan: the non-paraxial path takes amplitude plates only");
     if (o.path == FZP_PATH_AUTO) {
       // the split GEMMs cost 8 M (binary), 16 M (2- and 4-level phase) or
       // 24 M (complex) flops per sample, the FP64 Bluestein path a few hundred
@@ -253,6 +343,17 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     }
     p.roi_elems = roi;
 
+    // non-paraxial variant: the padded grid, its FFT factors and each
+    // instance's transfer function and zoom
+    const bool sa = o.path == FZP_PATH_SA_CZT;
+    if (sa) {
+      const fzp_status_t st = plan_sa(p, o.pad > 0.0 ? o.pad : 1.5);
+      if (st != FZP_OK) {
+        delete h;
+        return st;
+      }
+    }
+
     // stripe and chunk schedule
     const bool split = o.path == FZP_PATH_SPLIT_BF16;
     p.S = o.stripe_rows > 0 ? o.stripe_rows : (split ? 128 : 64);
@@ -283,7 +384,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
                     : (o.flags & FZP_FLAG_BIN_DEEP) ? 2 : 4;
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
     set_variant(p, p.bin_variant);
-    p.lanes_max = o.lanes > 0 ? o.lanes : 1;
+    p.lanes_max = o.lanes > 0 && !sa ? o.lanes : 1;  // the padded field is one buffer
     p.lanes = p.lanes_max;
     const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
     const size_t tbytes = split ? sizeof(float) * 2 * (size_t)nseg : sizeof(double) * 2;
@@ -297,6 +398,13 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       c = c / p.S * p.S;
       if (c < p.S) c = p.S;
       p.chunk_rows = c < N ? c : N;
+    }
+    if (sa) {
+      // the zoom runs over the rows of the padded grid
+      const int64_t Np = p.inst[0].sa.Np;
+      const int64_t c = o.chunk_rows > 0 ? o.chunk_rows
+                                         : (int64_t)(((size_t)512 << 20) / ((size_t)p.Mmax * sizeof(double2)));
+      p.chunk_rows = c < Np ? (c > 0 ? c : 1) : Np;
     }
     if (split && cplx && o.chunk_rows <= 0) {
       // the complex stripe planes (8 bytes per sample of a chunk) stay near
@@ -377,6 +485,17 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         ih.dev.Npad = npad;
       }
     }
+    if (sa) {
+      const SaDev &a = p.inst[0].sa;
+      p.off_twNp = off;
+      off = align256(off + (size_t)a.Np * sizeof(double2));
+      p.off_tw1 = off;
+      off = align256(off + (size_t)a.n1 * sizeof(double2));
+      p.off_tw2 = off;
+      off = align256(off + (size_t)a.n2 * sizeof(double2));
+      p.off_U1 = off;
+      off = align256(off + (size_t)a.Np * (size_t)a.Np * sizeof(double2));
+    }
     p.T_bytes = align256((size_t)p.chunk_rows * p.Mmax * tbytes);
     if (split) {
       p.bits_bytes = align256(fzp::split_bits_bytes(p.inst[0].dev, p.chunk_rows));
@@ -452,6 +571,26 @@ extern "C" fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *b
   return FZP_OK;
 }
 
+extern "C" fzp_status_t fzp_plan_geometry(fzp_plan_t h, int32_t k, fzp_geometry_t *out) {
+  if (!h || !out || k < 0 || k >= (int32_t)h->plan.inst.size())
+    return fail(FZP_E_INVAL, "fzp_plan_geometry: bad argument");
+  const Plan &p = h->plan;
+  // Eq. 3 at r = R: n = (2 / lambda0)(sqrt(f0^2 + R^2) - f0), without the cancellation
+  const double R = 0.5 * p.ap.D, f = p.ap.f0;
+  const double n = 2.0 * R * R / (p.ap.lambda0 * (std::sqrt(f * f + R * R) + f));
+  std::memset(out, 0, sizeof(*out));
+  out->zones_exact = n;
+  out->total_zones = (int64_t)std::floor(n);
+  if (p.opt.path == FZP_PATH_SA_CZT) {
+    const InstHost &ih = p.inst[k];
+    out->padded_n = ih.sa.Np;
+    out->fft_n1 = ih.sa.n1;
+    out->fft_n2 = ih.sa.n2;
+    out->zoom_distance = ih.Z / ih.lam;
+  }
+  return FZP_OK;
+}
+
 extern "C" void fzp_destroy(fzp_plan_t p) { delete p; }
 
 namespace {
@@ -473,6 +612,12 @@ void bind_tables(Plan &p, char *ws) {
     ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
     ih.dev.By = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_By) : nullptr;
     ih.dev.S = p.opt.path == FZP_PATH_SPLIT_BF16 && p.ap.levels == 2 ? (const double2 *)(ws + ih.off_S) : nullptr;
+    if (p.opt.path == FZP_PATH_SA_CZT) {
+      ih.sa.cr = ih.dev.cr;
+      ih.sa.twNp = (const double2 *)(ws + p.off_twNp);
+      ih.sa.tw1 = (const double2 *)(ws + p.off_tw1);
+      ih.sa.tw2 = (const double2 *)(ws + p.off_tw2);
+    }
   }
 }
 
@@ -533,6 +678,13 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
       hipError_t e = fzp::init_split_attributes();
       if (e != hipSuccess) return hip_fail("fzp_prepare: kernel attributes", e);
     }
+    if (p.opt.path == FZP_PATH_SA_CZT) {
+      hipError_t e = fzp::init_sa_attributes();
+      if (e == hipSuccess)
+        e = fzp::launch_sa_twiddles(p.inst[0].sa, (double2 *)(ws + p.off_twNp), (double2 *)(ws + p.off_tw1),
+                                    (double2 *)(ws + p.off_tw2), st);
+      if (e != hipSuccess) return hip_fail("fzp_prepare: padded-grid tables", e);
+    }
     p.prepared_ws = workspace;
     return FZP_OK;
   } catch (const std::exception &e) {
@@ -578,6 +730,43 @@ hipError_t ensure_aux(Plan &p) {
     p.aux_ev.push_back(ev);
   }
   return hipSuccess;
+}
+
+// Non-paraxial variant: the propagated padded field U1 of instance ih (seven
+// FFT passes with the transfer function), then the chirp-z zoom over U1's
+// rows in chunks of chunk_rows (row pass, then column pass into the ROI).
+fzp_status_t enqueue_sa(Plan &p, InstHost &ih, char *ws, double2 *roi, hipStream_t st) {
+  double2 *U1 = (double2 *)(ws + p.off_U1);
+  double2 *T = (double2 *)(ws + p.off_T[0]);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  size_t first = 0;
+  auto mark = [&](int kind, bool begin) -> hipError_t {
+    if (!p.profile) return hipSuccess;
+    if (begin) {
+      hipError_t pe = take_events(p, ea, eb, first);
+      return pe == hipSuccess ? hipEventRecord(ea, st) : pe;
+    }
+    const hipError_t pe = hipEventRecord(eb, st);
+    p.ev_marks.emplace_back(first, kind);
+    return pe;
+  };
+  hipError_t e = mark(2, true);
+  if (e == hipSuccess) e = fzp::launch_sa_field(ih.sa, U1, st);
+  if (e == hipSuccess) e = mark(2, false);
+  if (e != hipSuccess) return hip_fail("fzp_propagate_roi: padded field", e);
+  const int64_t Np = ih.sa.Np;
+  for (int64_t r0 = 0; r0 < Np; r0 += p.chunk_rows) {
+    const int64_t r1 = r0 + p.chunk_rows < Np ? r0 + p.chunk_rows : Np;
+    e = mark(0, true);
+    if (e == hipSuccess) e = fzp::launch_row_pass_stored(ih.dev, U1, r0, r1, T, st);
+    if (e == hipSuccess) e = mark(0, false);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi: zoom row pass", e);
+    e = mark(1, true);
+    if (e == hipSuccess) e = fzp::launch_col_pass(ih.dev, r0, r1, T, roi, st);
+    if (e == hipSuccess) e = mark(1, false);
+    if (e != hipSuccess) return hip_fail("fzp_propagate_roi: zoom column pass", e);
+  }
+  return FZP_OK;
 }
 
 // Rows [row_begin, row_end) of instance ih into its ROI, on stream st with the
@@ -719,6 +908,8 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
   Plan &p = h->plan;
   if (row_begin < 0 || row_end < row_begin || row_end > p.ap.N)
     return fail(FZP_E_INVAL, "fzp_propagate_roi_range: need 0 <= row_begin <= row_end <= N");
+  if (p.opt.path == FZP_PATH_SA_CZT && row_end > row_begin && (row_begin != 0 || row_end != p.ap.N))
+    return fail(FZP_E_UNSUPPORTED, "fzp_propagate_roi_range: the non-paraxial path takes whole apertures only");
   if (p.prepared_ws != workspace) {
     const fzp_status_t s = fzp_prepare(h, workspace, stream);
     if (s != FZP_OK) return s;
@@ -729,6 +920,17 @@ extern "C" fzp_status_t fzp_propagate_roi_range(fzp_plan_t h, void *workspace, d
   if (!accumulate) {
     e = fzp::launch_zero(roi_dev, 2 * p.roi_elems, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: zero", e);
+  }
+  if (p.opt.path == FZP_PATH_SA_CZT) {
+    // the angular spectrum needs the whole aperture at once
+    if (row_end <= row_begin) return FZP_OK;
+    if (row_begin != 0 || row_end != p.ap.N)
+      return fail(FZP_E_UNSUPPORTED, "fzp_propagate_roi_range: the non-paraxial path takes whole apertures only");
+    for (auto &ih : p.inst) {
+      const fzp_status_t s = enqueue_sa(p, ih, ws, (double2 *)roi_dev + ih.roi_off, st);
+      if (s != FZP_OK) return s;
+    }
+    return FZP_OK;
   }
   const int lanes = p.lanes < (int)p.inst.size() ? p.lanes : (int)p.inst.size();
   if (lanes <= 1) {
@@ -841,7 +1043,8 @@ extern "C" fzp_status_t fzp_propagate_resumable(fzp_plan_t h, void *workspace, d
   try {
     Plan &p = h->plan;
     const int64_t N = p.ap.N;
-    const int64_t chunk = p.chunk_rows > 0 ? p.chunk_rows : N;
+    // the non-paraxial path runs the whole aperture as one block
+    const int64_t chunk = p.opt.path == FZP_PATH_SA_CZT ? N : (p.chunk_rows > 0 ? p.chunk_rows : N);
     int64_t block = rows_per_checkpoint > 0 ? rows_per_checkpoint : chunk;
     block = (block + chunk - 1) / chunk * chunk;
     hipStream_t st = (hipStream_t)stream;

@@ -1,6 +1,7 @@
 """Host-side tests of the C ABI (no GPU needed): the library loads, exports
 every function that include/fzp.h declares, and validates its arguments."""
 import ctypes
+import math
 import os
 import re
 
@@ -34,7 +35,8 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.Aperture) == 48
     assert ctypes.sizeof(L.Crease) == 32
     assert ctypes.sizeof(L.Instance) == 56
-    assert ctypes.sizeof(L.Options) == 32
+    assert ctypes.sizeof(L.Options) == 40
+    assert ctypes.sizeof(L.Geometry) == 40
     assert ctypes.sizeof(L.Metrics) == 64
 
 
@@ -211,3 +213,37 @@ def test_graph_of_overlap_operand_plan_is_refused():
     st = lib.fzp_graph_create(plan._h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), ctypes.byref(g))
     assert st == L.FZP_E_UNSUPPORTED and not g.value
     assert b"OVERLAP_OPERAND" in lib.fzp_last_error()
+
+
+def test_non_paraxial_plan_geometry_and_validation():
+    """FZP_PATH_SA_CZT: the padded grid follows the pad rule of the oracle, factors
+    into two LDS lengths, the Eq. 3 zone count matches the oracle's root, and the
+    path refuses phase plates, bad pads and partial row ranges (before any device
+    call)."""
+    from oracle import sa_czt_oracle as S
+    lib = P.load_library()
+    for N, D, f, pad in ((4096, 2e-3, 10e-3, 0.0), (28672, 0.08, 1.5, 0.0), (1001, 1e-3, 5e-3, 2.0),
+                         (2048, 1e-3, 2e-3, 3.0)):
+        lam0 = 532e-9 if D == 0.08 else LAM0
+        plan = P.Plan(dict(D=D, f0=f, lambda0=lam0, N=N), [dict(lam=lam0, M=64)], path="sa", pad=pad,
+                      allow_undersampled=True)
+        g = plan.geometry(0)
+        assert g["padded_n"] == S.pad_size(N, pad or 1.5)
+        assert g["fft_n1"] * g["fft_n2"] == g["padded_n"] and g["fft_n1"] <= g["fft_n2"] <= 1024
+        assert abs(g["zones_exact"] / O.zone_count_exact(D, lam0, f) - 1) < 1e-12
+        assert g["total_zones"] == int(O.zone_count_exact(D, lam0, f))
+        # zoom distance Z / lambda = 4 pi |d| z / (k_max lambda) with the two-point fit at k_max = 2 k0 / 3
+        k0, kmax, c, d = S.fit_constants(lam0)
+        assert abs(g["zoom_distance"] / (4 * math.pi * abs(d) * f / (kmax * lam0)) - 1) < 1e-12
+    assert P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096), [dict(lam=LAM0, M=64)]).geometry()["padded_n"] == 0
+    base = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
+    with pytest.raises(P.FZPError) as e:
+        P.Plan(dict(base, levels=4), [dict(lam=LAM0, M=64)], path="sa")
+    assert e.value.status == L.FZP_E_UNSUPPORTED
+    for pad in (0.5, 9.0, float("nan")):
+        with pytest.raises(P.FZPError) as e:
+            P.Plan(base, [dict(lam=LAM0, M=64)], path="sa", pad=pad)
+        assert e.value.status == L.FZP_E_INVAL
+    plan = P.Plan(base, [dict(lam=LAM0, M=64)], path="sa")
+    st = lib.fzp_propagate_roi_range(plan._h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), 0, 1024, 0, None)
+    assert st == L.FZP_E_UNSUPPORTED

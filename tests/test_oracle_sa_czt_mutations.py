@@ -89,7 +89,7 @@ def m_sa_z_with_k0(ap, inst, radii="eq3", pad=1.5, k_fit=2.0 / 3.0, method="blue
     r = F.resolve(ap, inst)
     lam, z = r["lam"], r["z"]
     k0, kmax, c, d = S.fit_constants(lam, k_fit)
-    U1 = S.angular_spectrum_step(S.padded_aperture(ap, radii, pad), ap.dx, lam, z, k_fit)
+    U1 = S.angular_spectrum_step(S.padded_aperture(ap, radii, pad, inst), ap.dx, lam, z, k_fit)
     Z = 4.0 * np.pi * abs(d) * z / k0
     xq = F.roi_coords(inst.M, inst.x0, r["dx_out"])
     yp = F.roi_coords(inst.M, inst.y0, r["dx_out"])

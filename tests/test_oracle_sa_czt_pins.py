@@ -153,3 +153,16 @@ def test_pad_size_rule():
         # smallest such size
         assert all(not (c >= 1.5 * N and (c - N) % 2 == 0 and S._smooth(c)) for c in range(int(math.ceil(1.5 * N)), m))
     assert S.pad_size(4096) == 6144 and S.pad_size(28672) == 43200
+
+
+def test_zero_height_creases_and_constant_screen():
+    """The crease screen: zero heights leave the field bit for bit; a crease
+    whose profile is constant over the aperture (a very wide ridge through the
+    centre) only multiplies the field by its constant phase."""
+    ap = F.Aperture(D=1e-3, f0=5e-3, lambda0=LAM0, N=256)
+    base = S.sa_czt(ap, F.Instance(lam=LAM0, M=16))
+    z0 = S.sa_czt(ap, F.Instance(lam=LAM0, M=16, creases=np.array([[0.3, 1e-4, 2e-4, 0.0]])))
+    assert np.array_equal(base, z0)
+    H = 0.3 * LAM0
+    wide = S.sa_czt(ap, F.Instance(lam=LAM0, M=16, creases=np.array([[0.3, 0.0, 1e3, H]])))
+    assert rel_l2(wide, base * np.exp(2j * np.pi * H / LAM0)) < 1e-9
