@@ -16,7 +16,8 @@ Besides the headline it reports, on the same GPU: the 64-instance creased
 batch of the 20 mm element (graph-launched, autotuned, with the roofline of
 its complex-stripe GEMM), the 0.1 m 4- and 2-level phase plates
 (``ml100mm``, ``ml100mm_l2``), the 2 mm and 20 mm elements on both paths
-(``configs``), a reduced run of the learned surrogate (``surrogate``; the
+(``configs``), the non-paraxial path on the accuracy study's plate at
+N = 28672 (``sa_czt``), a reduced run of the learned surrogate (``surrogate``; the
 full 20k-solve run with ``--surrogate``), the CPU oracle on a sample of the
 workload (on every core this process may use), and on request the
 grid-convergence sweep of the accuracy study (``--convergence``).
@@ -60,6 +61,11 @@ def parse():
                     help="train and evaluate the learned surrogate at full size (20k + 1k CZT solves) instead "
                          "of the reduced run")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--no-sa", action="store_true",
+                    help="skip the non-paraxial path on the accuracy study's plate at N = 28672")
+    ap.add_argument("--sa-steps", type=int, default=3)
+    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs"], default=None,
+                    help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
     return ap.parse_args()
@@ -353,6 +359,68 @@ def run_configs(dev, steps: int = 3):
     return out
 
 
+def run_sa(args, dev):
+    """The non-paraxial path (FZP_PATH_SA_CZT) on the accuracy study's plate
+    (Sec. 4.1: binary, D = 0.08 m, f = 1.5 m, 532 nm, Eq. 3 radii) at its
+    largest grid N = 28672 (padded to 43200^2, 29.9 GB in HBM), ROI 512^2:
+    one propagation plus metrics per step.  Roofline of the padded-field
+    passes: HBM-bound, 13 sweeps of the padded field per propagation (the
+    first pass writes it, six passes read and write it).  The oracle is timed
+    on a 4096^2 sample of the same plate (padded to 6144^2) for context."""
+    import numpy as np
+    import torch
+    import paper_2609_01978_amd as P
+    from oracle import fzp_oracle as O
+    from oracle import sa_czt_oracle as S
+    from scipy import fft as sfft
+    D, f, lam, N, M = 0.08, 1.5, 532e-9, 28672, 512
+    plan = P.Plan(dict(D=D, f0=f, lambda0=lam, N=N), [dict(lam=lam, M=M)], path="sa")
+    g = plan.geometry()
+    ws, roi = plan.alloc(dev)
+    plan.prepare(ws)
+    plan.propagate(ws, roi)
+    plan.metrics(ws, roi)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.sa_steps):
+        plan.propagate(ws, roi)
+        m = plan.metrics(ws, roi)[0]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.sa_steps
+    pr = plan.profile_read(reset=True)
+    plan.profile(False)
+    log(f"sa_czt N={N}: {dt * 1e3:.1f} ms per propagation")
+    del ws, roi, plan
+    torch.cuda.empty_cache()
+    Np = g["padded_n"]
+    field_ms = pr["mask_ms"] / args.sa_steps
+    bytes_field = 13.0 * Np * Np * 16.0
+    ach = bytes_field / (field_ms * 1e-3) / 1e9
+    model, cores = host_cpu()
+    a = O.Aperture(D=D, f0=f, lambda0=lam, N=4096)
+    t1 = time.perf_counter()
+    with sfft.set_workers(cores):
+        S.sa_czt(a, O.Instance(lam=lam, M=M))
+    t_cpu = time.perf_counter() - t1
+    return {"workload": f"binary FZP with Eq. 3 radii, D={D} m f={f} m lambda=532 nm, N={N}^2 padded to {Np}^2 "
+                        f"({g['fft_n1']} x {g['fft_n2']} per axis), ROI {M}^2",
+            "steps": args.sa_steps, "ms_per_step": round(dt * 1e3, 3),
+            "gsamples_s": round(float(N) * N / dt / 1e9, 3),
+            "padded_gsamples_s": round(float(Np) * Np / dt / 1e9, 3),
+            "field_ms": round(field_ms, 3), "zoom_row_ms": round(pr["row_ms"] / args.sa_steps, 3),
+            "zoom_col_ms": round(pr["col_ms"] / args.sa_steps, 3),
+            "metrics": m, "zones_eq3": g["zones_exact"], "zoom_distance_m": g["zoom_distance"],
+            "roofline": dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                             frac=round(ach / PEAK_HBM_GBS, 4), kernel="k_sa_pass (7 launches)",
+                             bytes_per_step=bytes_field,
+                             work="13 sweeps of the padded float64 complex field per propagation"),
+            "cpu_oracle_sample": {"value": round(4096.0 * 4096 / t_cpu / 1e9, 5), "unit": "Gsamples/s",
+                                  "cores": cores, "cpu_model": model, "kind": "oracle",
+                                  "sample": f"the same plate on 4096^2 samples (padded 6144^2), {t_cpu:.1f} s"}}
+
+
 # Closed forms of the ideal Airy pattern (aberration-free circular pupil):
 # FWHM = 1.028994 lambda f / D (half maximum of (2 J1(v)/v)^2 at v = 1.61634),
 # main-lobe share 1 - J0(j11)^2 of the first order, which carries 1/pi^2 of the
@@ -427,6 +495,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
+
+    if args.only is not None:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
+               "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev)}[args.only]
+        print(json.dumps({args.only: run()}), flush=True)
         return
 
     w = workload(args.workload)
@@ -557,6 +633,8 @@ def main():
         out["ml100mm_l2"] = run_multilevel(args, dev, levels=2)
     if not args.no_configs:
         out["configs"] = run_configs(dev)
+    if not args.no_sa:
+        out["sa_czt"] = run_sa(args, dev)
     if args.convergence:
         out["convergence"] = run_convergence(dev)
     if args.surrogate or not args.no_surrogate:

@@ -114,7 +114,7 @@ typedef struct {
   double f0;         /* design focal length */
   double lambda0;    /* design wavelength (zone radii r_n^2 = n lambda0 f0) */
   double pitch;      /* sample pitch; 0 means D / N */
-  int64_t N;         /* samples per side, 1 .. 2^21 (FZP_PATH_SA_CZT: padded grid up to 2^20) */
+  int64_t N;         /* samples per side, 1 .. 2^24 (FZP_PATH_SA_CZT: padded grid up to 2^20) */
   int32_t centre_open; /* amplitude plates: 0 central zone opaque (odd zones open), 1 central
                           zone open; must be 0 for phase plates */
   int32_t levels;      /* 0: binary amplitude plate (Sec. 2.2).  2 .. 64: L-level phase plate
@@ -258,6 +258,15 @@ fzp_status_t fzp_metrics(fzp_plan_t p, void *workspace, const double *roi_dev,
 fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *block, int64_t *chunk_rows,
                            int32_t *stripe_rows, int32_t *path, int64_t *disc_samples,
                            double *kappa);
+
+/* Grid rule of the revised engine (Fig. 18 stage 1), the sampling of the
+ * paper's meter-class runs (Tables 1-4): the zone period at the rim
+ * Lambda_edge = lambda0 f0 / R (R = D/2) sampled s_samp times per phase step,
+ * pitch = Lambda_edge / (s_samp max(L, 2)), N = ceil(D / pitch) made odd (an
+ * axis sample).  levels 0 (amplitude plate) counts as L = 2; s_samp 0 = 4.
+ * Host only.  Errors: FZP_E_INVAL. */
+fzp_status_t fzp_grid_for_element(double D, double f0, double lambda0, int32_t levels, int32_t s_samp,
+                                  double *pitch, int64_t *N);
 
 /* Geometry of a plan.  zones_exact is the real root n of Eq. 3 at r = D/2,
  * (lambda0^2/4) n^2 + lambda0 f0 n = (D/2)^2, and total_zones its floor (the zone

@@ -43,7 +43,7 @@ STATIC_SCRATCH_BYTES = 64 << 20   # FZP_STATIC_SCRATCH_BYTES
 
 EXPORTED = [
     "fzp_plan", "fzp_plan_workspace_size", "fzp_roi_elements", "fzp_roi_offset", "fzp_prepare",
-    "fzp_propagate_roi", "fzp_propagate_roi_static", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_plan_geometry", "fzp_destroy",
+    "fzp_propagate_roi", "fzp_propagate_roi_static", "fzp_propagate_roi_range", "fzp_propagate_resumable", "fzp_metrics", "fzp_plan_info", "fzp_plan_geometry", "fzp_grid_for_element", "fzp_destroy",
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
     "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
     "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
@@ -143,6 +143,10 @@ def load_library() -> ctypes.CDLL:
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_double)]
     lib.fzp_plan_info.restype = st
+    lib.fzp_grid_for_element.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.fzp_grid_for_element.restype = st
     lib.fzp_plan_geometry.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Geometry)]
     lib.fzp_plan_geometry.restype = st
     lib.fzp_profile_enable.argtypes = [P, ctypes.c_int32]
@@ -450,6 +454,15 @@ class MLP:
     def adam_update(self, grads, lr: float, stream=None):
         _check(self._lib, self._lib.fzp_mlp_adam_update(self._h, _ptr(self.ws), _ptr(grads), float(lr),
                                                         _stream_handle(stream)))
+
+
+def grid_for_element(D: float, f0: float, lambda0: float, levels: int = 0, s_samp: int = 0):
+    """fzp_grid_for_element: (pitch, N) of the revised engine's grid rule."""
+    lib = load_library()
+    dx, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib, lib.fzp_grid_for_element(float(D), float(f0), float(lambda0), int(levels), int(s_samp),
+                                         ctypes.byref(dx), ctypes.byref(n)))
+    return dx.value, n.value
 
 
 def log_intensity(roi, n_complex: int, i0: float, floor: float, out, stream=None):

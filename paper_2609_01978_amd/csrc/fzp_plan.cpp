@@ -225,7 +225,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
       return fail(FZP_E_INVAL, "fzp_plan: D, f0 and lambda0 must be finite and positive");
     if (!(std::isfinite(ap->pitch) && ap->pitch >= 0.0)) return fail(FZP_E_INVAL, "fzp_plan: pitch must be >= 0");
-    if (ap->N < 1 || ap->N > (int64_t(1) << 21)) return fail(FZP_E_INVAL, "fzp_plan: N must be in 1 .. 2^21");
+    if (ap->N < 1 || ap->N > (int64_t(1) << 24)) return fail(FZP_E_INVAL, "fzp_plan: N must be in 1 .. 2^24");
     if (ap->centre_open != 0 && ap->centre_open != 1) return fail(FZP_E_INVAL, "fzp_plan: centre_open must be 0 or 1");
     if (ap->levels != 0 && (ap->levels < 2 || ap->levels > 64))
       return fail(FZP_E_INVAL, "fzp_plan: levels must be 0 (amplitude plate) or 2 .. 64 (phase plate)");
@@ -568,6 +568,24 @@ extern "C" fzp_status_t fzp_plan_info(fzp_plan_t p, int32_t *fft_len, int32_t *b
   if (path) *path = pl.opt.path;
   if (disc_samples) *disc_samples = pl.disc_samples;
   if (kappa) *kappa = pl.kappa;
+  return FZP_OK;
+}
+
+extern "C" fzp_status_t fzp_grid_for_element(double D, double f0, double lambda0, int32_t levels, int32_t s_samp,
+                                             double *pitch, int64_t *N) {
+  if (!pitch || !N) return fail(FZP_E_INVAL, "fzp_grid_for_element: NULL output");
+  if (!finite_pos(D) || !finite_pos(f0) || !finite_pos(lambda0) || levels < 0 || levels > 64 || s_samp < 0)
+    return fail(FZP_E_INVAL, "fzp_grid_for_element: bad argument");
+  const int32_t S = s_samp > 0 ? s_samp : 4;
+  const int32_t L = levels > 2 ? levels : 2;
+  const double edge = lambda0 * f0 / (0.5 * D);  // zone period at the rim
+  const double dx = edge / ((double)S * (double)L);
+  const double n = std::ceil(D / dx);
+  if (!(n < 9.0e15)) return fail(FZP_E_INVAL, "fzp_grid_for_element: grid too large");
+  int64_t nx = (int64_t)n;
+  if (nx % 2 == 0) ++nx;
+  *pitch = dx;
+  *N = nx;
   return FZP_OK;
 }
 

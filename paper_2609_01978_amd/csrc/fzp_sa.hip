@@ -28,8 +28,9 @@ namespace fzp {
 
 namespace {
 
-constexpr int kSaThreads = 256;
-constexpr int kSaSlots = 2048;  // complex elements per LDS buffer (two buffers)
+constexpr int kSaThreads = 512;
+constexpr int kSaSlots = 2048;                  // complex elements per LDS buffer (two buffers)
+constexpr int kSaEl = kSaSlots / kSaThreads;    // elements a thread moves to or from HBM
 
 // Small DFTs in registers, natural order: X[k] = sum_n x[n] e^{DIR 2 pi i n k / R}.
 template <int DIR>
@@ -107,7 +108,7 @@ __device__ __forceinline__ void dft_r(double2 v[8], int R) {
 struct Radices {
   int n, nst;
   int r[kSaMaxStages];
-  const double2 *tw;  // W_n^k = e^{-2 pi i k / n}, k < n
+  const double2 *tw;  // W_n^k = e^{-2 pi i k / n}, k < n (in LDS)
 };
 
 // G transforms of length n held in LDS at src[t * ld + s] (slot s fastest):
@@ -251,50 +252,76 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
                           : PASS == kYA                   ? (int64_t)n1 * Np
                                                           : Np;
   const int total = G * n;
-  // ---- load (or generate) with the twiddle of inverse A passes
+  // element k of this thread: e = tid + k kSaThreads -> (slot s, index t)
+  auto slot_of = [&](int e, int &sl, int &t) {
+    if (PASS == kXB) {
+      sl = e / n;
+      t = e % n;
+    } else {
+      sl = e % G;
+      t = e / G;
+    }
+  };
+  // ---- load (or generate) with the twiddle of inverse A passes; every load
+  // of the thread is issued before the first is used
   if (PASS == kXAgen && (o < a.off || o >= a.off + a.N)) {
     // a row outside the aperture: its transform is zero
-    for (int e = threadIdx.x; e < total; e += kSaThreads) {
-      const int s = e % G, t = e / G;
-      if (s < nslot) U[base + s + t * tstride] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      int sl, t;
+      const int e = threadIdx.x + k * kSaThreads;
+      slot_of(e, sl, t);
+      if (e < total && sl < nslot) U[base + sl + t * tstride] = make_double2(0.0, 0.0);
     }
     return;
   }
-  for (int e = threadIdx.x; e < total; e += kSaThreads) {
-    int s, t;
-    if (PASS == kXB) {
-      s = e / n;
-      t = e % n;
-    } else {
-      s = e % G;
-      t = e / G;
-    }
-    double2 v = make_double2(0.0, 0.0);
-    if (s < nslot) {
-      if (PASS == kXAgen) {
-        v = sa_aperture(a, o, u0 + s + (int64_t)n1 * t);
-      } else {
-        v = U[base + (PASS == kXB ? (int64_t)s * n : (int64_t)s) + t * tstride];
-        if (PASS == kXAinv) v = cmul(v, conj(a.twNp[(u0 + s) * t]));
-        if (PASS == kYA && DIR > 0) v = cmul(v, conj(a.twNp[o * t]));
+  double2 *twl = bufB + (size_t)n * ld;  // W_n^k of this pass's length
+  {
+    const double2 *twg = alen2 ? a.tw2 : a.tw1;
+    for (int k = threadIdx.x; k < n; k += kSaThreads) twl[k] = twg[k];
+  }
+  {
+    double2 v[kSaEl], w[kSaEl];
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      int sl, t;
+      const int e = threadIdx.x + k * kSaThreads;
+      slot_of(e, sl, t);
+      v[k] = make_double2(0.0, 0.0);
+      w[k] = make_double2(1.0, 0.0);
+      if (e < total && sl < nslot) {
+        if (PASS == kXAgen) {
+          v[k] = sa_aperture(a, o, u0 + sl + (int64_t)n1 * t);
+        } else {
+          v[k] = U[base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride];
+          if (PASS == kXAinv) w[k] = a.twNp[(u0 + sl) * t];
+          if (PASS == kYA && DIR > 0) w[k] = a.twNp[o * t];
+        }
       }
     }
-    bufA[t * ld + s] = v;
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      int sl, t;
+      const int e = threadIdx.x + k * kSaThreads;
+      slot_of(e, sl, t);
+      if (e < total) bufA[t * ld + sl] = (PASS == kXAinv || (PASS == kYA && DIR > 0)) ? cmul(v[k], conj(w[k])) : v[k];
+    }
   }
   __syncthreads();
-  const Radices fa{n, alen2 ? a.nst2 : a.nst1, {}, alen2 ? a.tw2 : a.tw1};
-  Radices f = fa;
+  Radices f{n, alen2 ? a.nst2 : a.nst1, {}, twl};
   for (int k = 0; k < kSaMaxStages; ++k) f.r[k] = alen2 ? a.rad2[k] : a.rad1[k];
   double2 *res = lds_fft<DIR>(bufA, bufB, G, ld, f);
   if (PASS == kYBfilt) {
     // res[t = k1][s]: ky = k2 + n2 k1 (k2 = o); x = u0 + s holds kx = x / n1 + n2 (x % n1)
-    for (int e = threadIdx.x; e < total; e += kSaThreads) {
-      const int s = e % G, t = e / G;
-      if (s < nslot) {
-        const int64_t x = u0 + s;
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      const int e = threadIdx.x + k * kSaThreads;
+      const int sl = e % G, t = e / G;
+      if (e < total && sl < nslot) {
+        const int64_t x = u0 + sl;
         const int64_t kx = x / n1 + (int64_t)n2 * (x % n1);
         const int64_t ky = o + (int64_t)n2 * t;
-        res[t * ld + s] = cmul(res[t * ld + s], sa_transfer(a, kx, ky));
+        res[t * ld + sl] = cmul(res[t * ld + sl], sa_transfer(a, kx, ky));
       }
     }
     __syncthreads();
@@ -302,20 +329,29 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
     res = lds_fft<+1>(res, other, G, ld, f);
   }
   // ---- store, with the twiddle of forward A passes
-  for (int e = threadIdx.x; e < total; e += kSaThreads) {
-    int s, t;
-    if (PASS == kXB) {
-      s = e / n;
-      t = e % n;
-    } else {
-      s = e % G;
-      t = e / G;
+  {
+    double2 w[kSaEl];
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      int sl, t;
+      const int e = threadIdx.x + k * kSaThreads;
+      slot_of(e, sl, t);
+      w[k] = make_double2(1.0, 0.0);
+      if (e < total && sl < nslot) {
+        if (PASS == kXAgen) w[k] = a.twNp[(u0 + sl) * t];
+        if (PASS == kYA && DIR < 0) w[k] = a.twNp[o * t];
+      }
     }
-    if (s >= nslot) continue;
-    double2 v = res[t * ld + s];
-    if (PASS == kXAgen) v = cmul(v, a.twNp[(u0 + s) * t]);
-    if (PASS == kYA && DIR < 0) v = cmul(v, a.twNp[o * t]);
-    U[base + (PASS == kXB ? (int64_t)s * n : (int64_t)s) + t * tstride] = v;
+#pragma unroll
+    for (int k = 0; k < kSaEl; ++k) {
+      int sl, t;
+      const int e = threadIdx.x + k * kSaThreads;
+      slot_of(e, sl, t);
+      if (e >= total || sl >= nslot) continue;
+      double2 v = res[t * ld + sl];
+      if (PASS == kXAgen || (PASS == kYA && DIR < 0)) v = cmul(v, w[k]);
+      U[base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride] = v;
+    }
   }
 }
 
@@ -344,7 +380,8 @@ int sa_group(int n, bool contiguous) {
   return g < 1 ? 1 : g;
 }
 
-size_t sa_lds_bytes(int n, int G) { return (size_t)2 * (size_t)n * (size_t)(G + 1) * sizeof(double2); }
+// two ping-pong buffers of n (G + 1) complex and the W_n table
+size_t sa_lds_bytes(int n, int G) { return ((size_t)2 * (size_t)n * (size_t)(G + 1) + (size_t)n) * sizeof(double2); }
 
 hipError_t launch_sa_twiddles(const SaDev &a, double2 *twNp, double2 *tw1, double2 *tw2, hipStream_t st) {
   const int64_t blocks = (a.Np + 255) / 256;
@@ -363,7 +400,8 @@ hipError_t launch_pass(const SaDev &a, double2 *U, hipStream_t st) {
   else if (PASS == kXB) wgs = (a.Np * a.n2 + G - 1) / G;
   else if (PASS == kYA) wgs = (int64_t)a.n1 * ((a.Np + G - 1) / G);
   else wgs = (int64_t)a.n2 * ((a.Np + G - 1) / G);
-  if (wgs > 0x7fffffffLL) return hipErrorInvalidValue;
+  // every element of a work-group's G transforms is one of its threads' kSaEl
+  if (wgs > 0x7fffffffLL || (int64_t)G * n > (int64_t)kSaEl * kSaThreads) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sa_pass<PASS, DIR>), dim3((unsigned)wgs), dim3(kSaThreads), sa_lds_bytes(n, G), st, a, U, G,
                      wgs);
   return hipGetLastError();
@@ -384,7 +422,7 @@ hipError_t launch_sa_field(const SaDev &a, double2 *U, hipStream_t st) {
 hipError_t init_sa_attributes() {
   static bool done = false;
   if (done) return hipSuccess;
-  const int bytes = 2 * kSaSlots * (int)sizeof(double2);
+  const int bytes = (2 * kSaSlots + 1024) * (int)sizeof(double2);
   hipError_t e = hipSuccess;
 #define FZP_ATTR(P, D)                                                                                        \
   if (e == hipSuccess)                                                                                        \

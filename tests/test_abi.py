@@ -68,7 +68,7 @@ def test_sampling_limit_eq6():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(ap=dict(D=-1.0)), dict(ap=dict(N=0)), dict(ap=dict(N=(1 << 21) + 1)), dict(ap=dict(centre_open=2)),
+    dict(ap=dict(D=-1.0)), dict(ap=dict(N=0)), dict(ap=dict(N=(1 << 24) + 1)), dict(ap=dict(centre_open=2)),
     dict(inst=dict(M=1)), dict(inst=dict(M=4096)), dict(inst=dict(lam=float("nan"))), dict(inst=dict(z=-1.0)),
     dict(inst=dict(creases=[(0.0, 0.0, 0.0, 1e-7)])),
 ])
@@ -247,3 +247,35 @@ def test_non_paraxial_plan_geometry_and_validation():
     plan = P.Plan(base, [dict(lam=LAM0, M=64)], path="sa")
     st = lib.fzp_propagate_roi_range(plan._h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), 0, 1024, 0, None)
     assert st == L.FZP_E_UNSUPPORTED
+
+
+def _grid_tables():
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", "v8_grid_tables.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                t, D, f, L, dx, nx = line.split()
+                rows.append((int(t), float(D), float(f), int(L), float(dx), int(nx)))
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in _grid_tables() if r[0] <= 4], ids=lambda r: f"table{r[0]}")
+def test_grid_for_element_reproduces_tables_1_to_4(row):
+    """The library's grid rule gives the printed pitch and N_x of Tables 1-4
+    (Sec. 7.1; 532 nm) and agrees with the oracle's rule."""
+    t, D, f, L, dx_um, nx = row
+    dx, n = P.grid_for_element(D, f, 532e-9, L)
+    assert n == nx and abs(dx * 1e6 - dx_um) <= 0.0006
+    assert (dx, n) == O.v8_grid(D, f, 532e-9, L)
+    # the plan takes that grid (a pitch of its own and N up to 2^24)
+    plan = P.Plan(dict(D=D, f0=f, lambda0=532e-9, N=n, pitch=dx, levels=L), [dict(lam=532e-9, M=64)])
+    assert plan.info()["disc_samples"] > 0.78 * n * n
+
+
+def test_grid_for_element_arguments():
+    assert P.grid_for_element(1.0, 5.0, 532e-9, 0) == P.grid_for_element(1.0, 5.0, 532e-9, 2)
+    with pytest.raises(P.FZPError):
+        P.grid_for_element(-1.0, 5.0, 532e-9, 4)
+    with pytest.raises(P.FZPError):
+        P.Plan(dict(D=1.0, f0=5.0, lambda0=532e-9, N=(1 << 24) + 1), [dict(lam=532e-9, M=64)],
+               allow_undersampled=True)

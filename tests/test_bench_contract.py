@@ -25,7 +25,7 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.gpu
 def test_json_line_at_the_small_workload():
     r = run_bench("--workload", "fzp2mm", "--steps", "1", "--warmup", "0", "--no-batch", "--no-multilevel",
-                  "--no-cpu-baseline", "--no-configs", "--no-surrogate", "--fp64-steps", "1", "--fp64-warmup", "0")
+                  "--no-cpu-baseline", "--no-configs", "--no-surrogate", "--no-sa", "--fp64-steps", "1", "--fp64-warmup", "0")
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
     assert len(lines) == 1
