@@ -17,7 +17,9 @@ from typing import Iterable, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfzp.so")
+# FZP_LIBRARY names another build of the same library (e.g. the host-sanitized
+# one of build.py --host-sanitize); the default is the in-tree build
+LIB_PATH = os.environ.get("FZP_LIBRARY") or os.path.join(_HERE, "libfzp.so")
 
 FZP_OK = 0
 FZP_E_INVAL = -1

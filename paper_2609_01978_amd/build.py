@@ -1,6 +1,7 @@
 """Build the HIP library ``libfzp.so`` for gfx950 in-tree.
 
     python -m paper_2609_01978_amd.build        # or paper_2609_01978_amd.build.build()
+    python -m paper_2609_01978_amd.build --host-sanitize OUT.so   # host ASan + UBSan variant
 """
 from __future__ import annotations
 
@@ -37,20 +38,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into paper_2609_01978_amd/libfzp.so (always rebuilds)."""
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build (device code is
+# built as usual): every -fsanitize applies to the host pass only.
+HOST_SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                       "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                       "-g"]
+
+
+def build(verbose: bool = False, out: str = LIB, host_sanitize: bool = False) -> str:
+    """Compile every source into `out` (default paper_2609_01978_amd/libfzp.so;
+    always rebuilds).  host_sanitize builds the host code with ASan and UBSan
+    (load it with the sanitizer runtime preloaded and FZP_LIBRARY=<out>)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *srcs, "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *(HOST_SANITIZE_FLAGS if host_sanitize else []), "-I", INCLUDE, "-I", CSRC,
+           *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libfzp.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) == 3 and sys.argv[1] == "--host-sanitize":
+        print(build(verbose=True, out=os.path.abspath(sys.argv[2]), host_sanitize=True))
+    else:
+        print(build(verbose=True))
