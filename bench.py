@@ -289,8 +289,8 @@ def run_multilevel(args, dev, levels=None):
         if path == "split":
             # the row GEMM's own time (HIP events around its launches, one more
             # propagation): 8 M flops per disc sample for a 2-level plate (the
-            # binary GEMM of its odd zones), 16 M for a 4-level plate (hi planes
-            # only), 24 M otherwise
+            # binary GEMM of its odd zones), 16 M for a 4-level plate (two binary
+            # GEMMs: the odd zones and the levels 1 and 2), 24 M otherwise
             plan.profile(True)
             plan.profile_read(reset=True)
             plan.propagate(ws, roi)
@@ -302,7 +302,7 @@ def run_multilevel(args, dev, levels=None):
             ach = flops / (pr["row_ms"] * 1e-3) / 1e12
             res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS,
                                          unit="TFLOP/s", frac=round(ach / PEAK_BF16_TFLOPS, 4),
-                                         kernel="k_row_pass_split" if L == 2 else "k_row_pass_split_cplx",
+                                         kernel="k_row_pass_split" if L in (2, 4) else "k_row_pass_split_cplx",
                                          launch_ms=round(
                                              pr["row_ms"] / max(pr["row_launches"], 1), 3),
                                          work=f"{per / w['M']:.0f} M flops per disc sample")

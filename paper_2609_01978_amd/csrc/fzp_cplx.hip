@@ -22,15 +22,8 @@ constexpr int kCThreads = 512;
 // stage's), then barrier: N = 6 with all four stripe planes, 4 with the hi
 // planes only.
 template <int N> __device__ __forceinline__ void stage_barrier() {
-  static_assert(N == 4 || N == 6, "add the count");
-  if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-  if constexpr (N == 4) asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-// A 2- or 4-level phase plate without creases has stripe values 0, +-1, +-i:
-// exact in BF16, so its lo planes are zero and are neither written nor read.
-__host__ __device__ __forceinline__ bool stripe_exact(const InstDev &d) {
-  return (d.levels == 2 || d.levels == 4) && d.n_creases == 0;
+  static_assert(N == 6, "add the count");
+  asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -96,9 +89,9 @@ __device__ __forceinline__ void sincos_turns(float t, float &sn, float &cs) {
 // instruction; the same result as the integer rounding of the operand table).
 __device__ __forceinline__ uint16_t bf16_cvt(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-// PHASE: an L-level phase plate (levels != 0); EXACT: its values are exact in
-// BF16 (stripe_exact), so only the hi planes are written.
-template <bool PHASE, bool EXACT>
+// PHASE: an L-level phase plate (levels != 0).  Crease-free 2- and 4-level
+// plates never come here: they are sums of binary masks (k_col_operand).
+template <bool PHASE>
 __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
                                                      int64_t rows_pad, int64_t kb0, int64_t nkb,
                                                      uint16_t *__restrict__ G) {
@@ -190,14 +183,7 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         float sn, cs;
-        if constexpr (EXACT) {
-          // -l/L turns with L = 2 or 4: a whole number q of clockwise quarter turns
-          const int q = (int)rintf(-4.0f * turns[e + u]) & 3;
-          cs = q == 0 ? 1.0f : (q == 2 ? -1.0f : 0.0f);
-          sn = q == 3 ? 1.0f : (q == 1 ? -1.0f : 0.0f);
-        } else {
-          sincos_turns(turns[e + u], sn, cs);
-        }
+        sincos_turns(turns[e + u], sn, cs);
         const bool o = (open >> (e + u)) & 1u;
         const float gr = o ? cs : 0.0f, gi = o ? sn : 0.0f;
         const uint16_t rh = bf16_cvt(gr), ih = bf16_cvt(gi);
@@ -213,7 +199,6 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      if ((v & 1) && EXACT) continue;
       u32x4 *dst = (u32x4 *)(G + v * plane + (kb * rows_pad + rl) * 16);
       dst[0] = u32x4{w[v][0], w[v][1], w[v][2], w[v][3]};
       dst[1] = u32x4{w[v][4], w[v][5], w[v][6], w[v][7]};
@@ -237,13 +222,10 @@ __device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
 // seg_len_c rows, no chord), the A operand the column kernel matrix B_y and
 // the B operand the chunk's row-pass result T (see k_col_operand).  8 waves
 // in a 4 (rows) x 2 (columns) grid, each 64 x 128 = 2 x 4 MFMA 32x32 blocks
-// (128 float32 accumulators per lane), 6 MFMAs per block per K-step (4 when
-// GLO is false).  Stripe and table slabs move HBM -> LDS by direct copies into a
-// 3-deep ring, 2 stages ahead, one barrier per stage.
-// GLO = false: the stripe planes' lo parts are zero (a 2- or 4-level phase
-// plate without creases: every value is 0, +-1 or +-i, exact in BF16), so the
-// g_lo . A_hi products are skipped (4 MFMAs per block per K-step).
-template <bool COL, bool GLO = true>
+// (128 float32 accumulators per lane), 6 MFMAs per block per K-step.  Stripe
+// and table slabs move HBM -> LDS by direct copies into a 3-deep ring, 2
+// stages ahead, one barrier per stage.
+template <bool COL>
 __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
     InstDev d, int64_t row_begin, int64_t row_end, int n_rt, int n_ct, int seg_lo, int n_seg,
     const uint16_t *__restrict__ G, int64_t rows_pad, int64_t kb0, int64_t nkb, float *__restrict__ T,
@@ -288,15 +270,12 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   // holds global half chalf(row, L & 1).  Table columns past 2M read column 0:
   // they feed only accumulator columns that are never stored.
   const int64_t plane = nkb * rows_pad * 16;
-  // without lo planes (GLO false) each wave copies two pieces of the hi planes
-  // (re_hi = pieces 0-7, im_hi = pieces 16-23)
-  constexpr int NG = GLO ? 4 : 2;
+  constexpr int NG = 4;
   const uint16_t *gsrc[NG];
   int gx[NG];
 #pragma unroll
   for (int j = 0; j < NG; ++j) {
-    const int h = 2 * wave + j;
-    const int x = GLO ? 4 * wave + j : (h >> 3) * 16 + (h & 7);
+    const int x = 4 * wave + j;
     gx[j] = x;
     const int row = (x & 7) * 32 + (lane >> 1);
     gsrc[j] = G + (x >> 3) * plane + ((int64_t)rt * kCTR + row) * 16 + 8 * chalf(row, lane & 1);
@@ -377,14 +356,12 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bls[cb], acc[rb][cb], 0, 0, 0);
         }
-        if constexpr (GLO) {
-          const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
-          const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
+        const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
+        const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
-          }
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
         }
       }
       stage_barrier<NG + 2>();
@@ -482,28 +459,44 @@ __global__ __launch_bounds__(256) void k_build_col_table(InstDev d, int64_t rows
 // 128-byte run per plane (one 512-byte run per work-group).
 // With S (a 2-level plate) the partial planes hold T_mask and the operand is
 // T_disc - 2 T_mask, T_disc = S[hi] - S[lo] over row j's disc chord [lo, hi).
+// With S and T2 (a 4-level plate) T holds the odd zones' T_u and T2 the
+// second mask's T_v, and the operand is T_disc - (1 - i) T_u - (1 + i) T_v:
+//   re: D_re - (U_re + U_im) - (V_re - V_im),  im: D_im - (U_im - U_re) - (V_im + V_re).
+__device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
+  double v = 0.0;
+  int sgi = 0;
+  for (; sgi + 4 <= nseg; sgi += 4) {
+    const float a0 = src[(int64_t)sgi * seg_stride_f], a1 = src[(int64_t)(sgi + 1) * seg_stride_f];
+    const float a2 = src[(int64_t)(sgi + 2) * seg_stride_f], a3 = src[(int64_t)(sgi + 3) * seg_stride_f];
+    v += (double)a0;
+    v += (double)a1;
+    v += (double)a2;
+    v += (double)a3;
+  }
+  for (; sgi < nseg; ++sgi) v += (double)src[(int64_t)sgi * seg_stride_f];
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, int64_t row_end,
                                                      const float *__restrict__ T, int nseg, int64_t seg_stride_f,
                                                      int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb,
-                                                     const double2 *__restrict__ S, int64_t N, double kmax) {
+                                                     const double2 *__restrict__ S, int64_t N, double kmax,
+                                                     const float *__restrict__ T2) {
   const int64_t kk = blockIdx.x * (int64_t)32 + (threadIdx.x & 31);
   const int c = blockIdx.y * 8 + (threadIdx.x >> 5);
   if (kk >= KB || c >= M2) return;
   const int64_t j = kB0 + kk;
   uint16_t h = 0, l = 0;
   if (j >= row_begin && j < row_end) {
-    const float *src = T + (int64_t)c * rs + (j - row_begin);
-    double v = 0.0;
-    int sgi = 0;
-    for (; sgi + 4 <= nseg; sgi += 4) {
-      const float a0 = src[(int64_t)sgi * seg_stride_f], a1 = src[(int64_t)(sgi + 1) * seg_stride_f];
-      const float a2 = src[(int64_t)(sgi + 2) * seg_stride_f], a3 = src[(int64_t)(sgi + 3) * seg_stride_f];
-      v += (double)a0;
-      v += (double)a1;
-      v += (double)a2;
-      v += (double)a3;
+    double v = sum_segments(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+    if (T2) {
+      // c and its partner column c ^ 1 (re / im of the same ROI column)
+      const double u_o = sum_segments(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_s = sum_segments(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_o = sum_segments(T2 + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      // re (c even): U_re + U_im + V_re - V_im; im (c odd): U_im - U_re + V_im + V_re
+      v = (c & 1) ? (v - u_o) + (v_s + v_o) : (v + u_o) + (v_s - v_o);
     }
-    for (; sgi < nseg; ++sgi) v += (double)src[(int64_t)sgi * seg_stride_f];
     if (S) {
       const double cj = (double)(2 * j - N + 1);
       const double rem = kmax - cj * cj;
@@ -518,7 +511,7 @@ __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, 
         const double2 a = S[hi * (M2 / 2) + (c >> 1)], b = S[lo * (M2 / 2) + (c >> 1)];
         disc = (c & 1) ? a.y - b.y : a.x - b.x;
       }
-      v = disc - 2.0 * v;
+      v = T2 ? disc - v : disc - 2.0 * v;
     }
     h = bf16_rne((float)v);
     l = bf16_rne((float)(v - (double)__uint_as_float((uint32_t)h << 16)));
@@ -558,9 +551,6 @@ hipError_t init_cplx_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kCLdsBytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<false, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kCLdsBytes);
   return e;
 }
 
@@ -591,15 +581,10 @@ hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_e
   if (gy > nkb) gy = nkb;
   if (gy > 65535) gy = 65535;
   const dim3 grid((unsigned)gx, (unsigned)gy);
-  if (stripe_exact(d))
-    hipLaunchKernelGGL((k_stripe_cplx<true, true>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
-                       nkb, G);
-  else if (d.levels != 0)
-    hipLaunchKernelGGL((k_stripe_cplx<true, false>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
-                       nkb, G);
+  if (d.levels != 0)
+    hipLaunchKernelGGL(k_stripe_cplx<true>, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
   else
-    hipLaunchKernelGGL((k_stripe_cplx<false, false>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
-                       nkb, G);
+    hipLaunchKernelGGL(k_stripe_cplx<false>, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
   return hipGetLastError();
 }
 
@@ -619,15 +604,9 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
   const int64_t grid = (Gn + 255) / 256 * 256;
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
-  // 2- and 4-level phase plates without creases: stripe values exact in BF16
-  if (stripe_exact(d))
-    hipLaunchKernelGGL((k_row_pass_split_cplx<false, false>), dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st,
-                       d, row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
-                       2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
-  else
-    hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
-                       row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
-                       2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
+                     row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
+                     2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -738,6 +717,8 @@ __global__ __launch_bounds__(256) void k_prefix_add(int M, int64_t N, const doub
 
 bool two_level_fast(const InstDev &d) { return d.levels == 2 && d.n_creases == 0 && d.S != nullptr; }
 
+bool four_level_fast(const InstDev &d) { return d.levels == 4 && d.n_creases == 0 && d.S != nullptr; }
+
 size_t prefix_table_bytes(int M, int64_t Npad) {
   const int64_t nb = (Npad + kPrefixBlock - 1) / kPrefixBlock;
   return (size_t)(Npad + 1 + nb) * (size_t)M * sizeof(double2);
@@ -766,7 +747,8 @@ hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st
 }
 
 hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
-                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st) {
+                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st,
+                                 const float2 *T2) {
   if (row_end <= row_begin || nseg <= 0) return hipSuccess;
   const int M = d.M, M2 = 2 * M;
   const ColSchedule c = col_schedule(M, row_begin, row_end);
@@ -774,7 +756,8 @@ hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t ro
   const int64_t rs = seg_stride / M;
   hipLaunchKernelGGL(k_col_operand, dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
                      row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
-                     two_level_fast(d) ? d.S : nullptr, d.N, d.kmax);
+                     two_level_fast(d) || four_level_fast(d) ? d.S : nullptr, d.N, d.kmax,
+                     four_level_fast(d) ? (const float *)T2 : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = init_split_attributes();

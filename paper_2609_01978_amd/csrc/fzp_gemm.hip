@@ -64,8 +64,14 @@ __global__ __launch_bounds__(256) void k_build_split_table(InstDev d, uint16_t *
 // single float64 product the reference rule uses (Sec. 2.2, Eq. 4).  Each
 // element is evaluated once here instead of once per GEMM column tile.
 // ---------------------------------------------------------------------------
+// FOUR: the two masks of a 4-level plate in one pass: with z = floor(K kappa_L),
+// kappa_L = 2 kappa (exactly, so z >> 1 = floor(K kappa)), the level is z mod 4;
+// `bits` gets the odd zones (z >> 1) & 1 = levels 2 and 3, `bits2` the levels 1
+// and 2, (z xor (z >> 1)) & 1 (a sample's (-i)^l is then
+// 1 - (1 - i) odd - (1 + i) half, see k_col_operand).
+template <bool FOUR>
 __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin, int64_t row_end, int64_t rows_pad,
-                                                   int W, uint32_t *__restrict__ bits) {
+                                                   int W, uint32_t *__restrict__ bits, uint32_t *__restrict__ bits2) {
   const int64_t N = d.N;
   const int Nm1 = (int)(N - 1);
   const double kappa = d.kappa;
@@ -94,22 +100,33 @@ __global__ __launch_bounds__(256) void k_mask_bits(InstDev d, int64_t row_begin,
   const int w0 = blockIdx.y * 64, w1 = min(w0 + 64, wend);
   for (int w = w0; w < w1; ++w) {
     const int i0 = 32 * w;
-    uint32_t v = 0;
+    uint32_t v = 0, v2 = 0;
     if (i0 < rhi && i0 + 32 > rlo) {
       double ci = (double)(2 * i0 - Nm1);
 #pragma unroll
       for (int e = 0; e < 32; ++e) {
         const double K = fma(ci, ci, bj);
-        const int zone = (int)(K * kappa);
-        v |= ((uint32_t)zone & 1u) << e;
+        if constexpr (FOUR) {
+          const int z = (int)(K * d.kappa_l);
+          v |= ((uint32_t)(z >> 1) & 1u) << e;
+          v2 |= ((uint32_t)(z ^ (z >> 1)) & 1u) << e;
+        } else {
+          const int zone = (int)(K * kappa);
+          v |= ((uint32_t)zone & 1u) << e;
+        }
         ci += 2.0;
       }
       const int lo = min(max(rlo - i0, 0), 32), hi = min(max(rhi - i0, 0), 32);
       const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
       v = (v ^ flip) & valid;
+      v2 &= valid;
     }
     bits[(int64_t)w * rows_pad + rl] = v;
     if (mirror) bits[(int64_t)(W - 1 - w) * rows_pad + rl] = __builtin_bitreverse32(v);
+    if constexpr (FOUR) {
+      bits2[(int64_t)w * rows_pad + rl] = v2;
+      if (mirror) bits2[(int64_t)(W - 1 - w) * rows_pad + rl] = __builtin_bitreverse32(v2);
+    }
   }
 }
 
@@ -484,14 +501,19 @@ void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &
   seg_hi = (int)((hi - 1) / d.seg_len) + 1;
 }
 
-hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st) {
+hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st,
+                            uint32_t *bits2) {
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
   const int W = (int)(d.Npad / 32);
   const int64_t rows_pad = bits_rows_pad(rows);
   const int wend = (int64_t)32 * W == d.N ? W / 2 : W;  // mirrored halves (see k_mask_bits)
   const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)((wend + 63) / 64));
-  hipLaunchKernelGGL(k_mask_bits, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, W, bits);
+  if (bits2)
+    hipLaunchKernelGGL(k_mask_bits<true>, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, W, bits, bits2);
+  else
+    hipLaunchKernelGGL(k_mask_bits<false>, grid, dim3(256), 0, st, d, row_begin, row_end, rows_pad, W, bits,
+                       (uint32_t *)nullptr);
   return hipGetLastError();
 }
 

@@ -118,6 +118,7 @@ struct Plan {
   // stripe buffers, one set per lane: row-pass result T, zone-mask bits and
   // complex stripe planes (split path)
   size_t T_bytes = 0, bits_bytes = 0, G_bytes = 0, Tb_bytes = 0, C_bytes = 0;
+  int32_t mask_sets = 1;  // binary masks (mask bits and T planes) per chunk: 2 for 4-level plates
   std::vector<size_t> off_T, off_bits, off_G, off_Tb, off_C;
   int32_t lanes_max = 1, lanes = 1;
   int64_t seg_len = 0;  // split path K segment (all instances)
@@ -170,7 +171,10 @@ size_t split_bits_bytes(const InstDev &d, int64_t chunk_rows);  // zone-mask bit
 // K segments [seg_lo, seg_hi) holding disc samples of rows [row_begin, row_end);
 // the split row pass writes exactly these partials, the first at T.
 void split_seg_range(const InstDev &d, int64_t row_begin, int64_t row_end, int &seg_lo, int &seg_hi);
-hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st);
+// bits2 (4-level plates, see four_level_fast): both masks in one pass, the odd
+// zones into bits and the levels 1 and 2 into bits2
+hipError_t launch_mask_bits(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st,
+                            uint32_t *bits2 = nullptr);
 // Deformed (complex) stripes on the split path: the BF16 hi/lo stripe planes of
 // one chunk (split_stripe_bytes for chunk_rows rows), then the complex GEMM.
 void split_chunk_chord(const InstDev &d, int64_t row_begin, int64_t row_end, int64_t &lo, int64_t &hi);
@@ -195,10 +199,17 @@ hipError_t launch_build_col_table(const InstDev &d, uint16_t *By, hipStream_t st
 // GEMM and T_disc = S[hi] - S[lo] over each row's disc chord from float64
 // prefix sums of the row kernel (prefix_table_bytes, built once per workspace).
 bool two_level_fast(const InstDev &d);
+// 4-level phase plates without creases on the split path: with the level l of
+// a disc sample, (-i)^l = 1 - (1 - i) [l in {2, 3}] - (1 + i) [l in {1, 2}], so
+// T = T_disc - (1 - i) T_odd - (1 + i) T_half with two binary-stripe GEMMs (the
+// odd zones, and levels 1 and 2) and T_disc from the same prefix sums.
+bool four_level_fast(const InstDev &d);
 size_t prefix_table_bytes(int M, int64_t Npad);
 hipError_t launch_build_prefix_table(const InstDev &d, double2 *S, hipStream_t st);
+// T2 (4-level plates): the partial planes of the second mask's GEMM, laid out as T.
 hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t row_end, const float2 *T, int nseg,
-                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st);
+                                 int64_t seg_stride, uint16_t *Tb, float *C, double2 *roi, hipStream_t st,
+                                 const float2 *T2 = nullptr);
 // Non-paraxial variant (fzp_sa.hip, fzp_fft.hip): twiddle tables, the
 // propagated padded field U1 by seven passes of LDS FFTs, and the CZT zoom's
 // row pass over U1's rows (the column pass is launch_col_pass).

@@ -219,7 +219,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       }
       int limit = 128;
       if ((ap->levels == 0 || ap->levels == 2) && !creased) limit = 1024;  // binary GEMM
-      else if (ap->levels == 0 || (ap->levels == 4 && !creased)) limit = 256;
+      else if (ap->levels == 0 || (ap->levels == 4 && !creased)) limit = 256;  // two binary GEMMs, or complex
       o.path = m16 && mmax <= limit ? FZP_PATH_SPLIT_BF16 : FZP_PATH_FP64_BLUESTEIN;
     }
     if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
@@ -361,10 +361,14 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       delete h;
       return fail(FZP_E_INVAL, "fzp_plan: split path stripe_rows must be 64, 128 or 256");
     }
-    bool cplx = false;  // split path with complex stripes (creases or a phase plate)
+    // split path with complex stripes: creases, or a phase plate other than the
+    // 2- and 4-level ones (which run on the binary kernels, see four_level_fast)
+    bool cplx = false;
     if (split)
-      for (const auto &ih : p.inst)
-        cplx = cplx || ih.in.n_creases > 0 || (ap->levels != 0 && ap->levels != 2);
+      for (const auto &ih : p.inst) {
+        cplx = cplx || ih.in.n_creases > 0 || (ap->levels != 0 && ap->levels != 2 && ap->levels != 4);
+        if (ap->levels == 4 && ih.in.n_creases == 0) p.mask_sets = 2;
+      }
     if (split)
       for (const auto &ih : p.inst)
         if (ih.in.M % 16 != 0) {
@@ -461,7 +465,7 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         if (ih.table_owner == k) {
           ih.off_A = off;
           off = align256(off + (size_t)2 * 2 * ih.in.M * npad * sizeof(uint16_t));
-          if (ap->levels == 2) {  // 2-level plates: prefix sums of the same kernel
+          if (ap->levels == 2 || ap->levels == 4) {  // 2- and 4-level plates: prefix sums of the same kernel
             ih.off_S = off;
             off = align256(off + fzp::prefix_table_bytes(ih.in.M, npad));
           }
@@ -507,11 +511,11 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
     }
     for (int l = 0; l < p.lanes_max; ++l) {
       p.off_T.push_back(off);
-      off += p.T_bytes;
+      off += (size_t)p.mask_sets * p.T_bytes;
       // two operand buffers when chunk c+1's operand is made during chunk c
       const size_t nbuf = (o.flags & FZP_FLAG_OVERLAP_OPERAND) ? 2 : 1;
       p.off_bits.push_back(off);
-      off += nbuf * p.bits_bytes;
+      off += nbuf * (size_t)p.mask_sets * p.bits_bytes;
       p.off_G.push_back(off);
       off += nbuf * p.G_bytes;
       p.off_Tb.push_back(off);
@@ -629,7 +633,9 @@ void bind_tables(Plan &p, char *ws) {
     ih.dev.lev = (const double2 *)(ws + ih.off_cr + (ih.creases.size() + 1) * sizeof(fzp::CreaseDev));
     ih.dev.A = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_A) : nullptr;
     ih.dev.By = p.opt.path == FZP_PATH_SPLIT_BF16 ? (const uint16_t *)(ws + ih.off_By) : nullptr;
-    ih.dev.S = p.opt.path == FZP_PATH_SPLIT_BF16 && p.ap.levels == 2 ? (const double2 *)(ws + ih.off_S) : nullptr;
+    ih.dev.S = p.opt.path == FZP_PATH_SPLIT_BF16 && (p.ap.levels == 2 || p.ap.levels == 4)
+                   ? (const double2 *)(ws + ih.off_S)
+                   : nullptr;
     if (p.opt.path == FZP_PATH_SA_CZT) {
       ih.sa.cr = ih.dev.cr;
       ih.sa.twNp = (const double2 *)(ws + p.off_twNp);
@@ -796,10 +802,14 @@ fzp_status_t enqueue_sa(Plan &p, InstHost &ih, char *ws, double2 *roi, hipStream
 fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2 *roi, int64_t row_begin,
                               int64_t row_end, hipStream_t st) {
   const bool split = p.opt.path == FZP_PATH_SPLIT_BF16;
-  // complex stripes: creases, or a phase plate other than the 2-level one
-  // (which runs as disc - 2 mask on the binary kernels)
-  const bool cplx = split && (ih.dev.n_creases > 0 || (ih.dev.levels != 0 && !fzp::two_level_fast(ih.dev)));
+  // complex stripes: creases, or a phase plate other than the 2- and 4-level
+  // ones (disc - 2 mask, disc - (1 - i) odd - (1 + i) half: binary kernels)
+  const bool four = split && fzp::four_level_fast(ih.dev);
+  const bool cplx = split && (ih.dev.n_creases > 0 ||
+                              (ih.dev.levels != 0 && !fzp::two_level_fast(ih.dev) && !four));
   void *T = ws + p.off_T[lane];
+  void *T2 = four ? ws + p.off_T[lane] + p.T_bytes : nullptr;  // the second mask's partial planes
+  const size_t bits_set = (size_t)p.mask_sets * p.bits_bytes;   // one operand buffer
   hipError_t e;
   // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples
   struct Chunk {
@@ -861,7 +871,9 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
       pe = cplx ? fzp::launch_stripe_cplx(ih.dev, chunks[i].r0, chunks[i].r1,
                                           (uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), ax)
                 : fzp::launch_mask_bits(ih.dev, chunks[i].r0, chunks[i].r1,
-                                        (uint32_t *)(ws + p.off_bits[lane] + b * p.bits_bytes), ax);
+                                        (uint32_t *)(ws + p.off_bits[lane] + b * bits_set), ax,
+                                        four ? (uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes)
+                                             : nullptr);
     if (pe == hipSuccess) pe = end_mark(2, ax);
     if (pe == hipSuccess && overlap) pe = hipEventRecord(ev[1 + b], ax);
     return pe;
@@ -896,9 +908,13 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     if (cplx)
       e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride,
                                           (const uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), st);
-    else if (split)
+    else if (split) {
       e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride,
-                                     (const uint32_t *)(ws + p.off_bits[lane] + b * p.bits_bytes), st);
+                                     (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set), st);
+      if (e == hipSuccess && four)
+        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T2, seg_stride,
+                                       (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes), st);
+    }
     else
       e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: row pass", e);
@@ -908,7 +924,8 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
     if (split)
       e = fzp::launch_col_pass_split(ih.dev, r0, r1, (const float2 *)T, chunks[i].nseg, seg_stride,
-                                     (uint16_t *)(ws + p.off_Tb[lane]), (float *)(ws + p.off_C[lane]), roi, st);
+                                     (uint16_t *)(ws + p.off_Tb[lane]), (float *)(ws + p.off_C[lane]), roi, st,
+                                     (const float2 *)T2);
     else
       e = fzp::launch_col_pass(ih.dev, r0, r1, (const double2 *)T, roi, st);
     if (e == hipSuccess) e = end_mark(1, st);
