@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 2 mm and 20 mm elements (both paths, full aperture)")
     ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the reduced surrogate run (4096 + 512 + 512 CZT solves, 30 epochs)")
+                    help="skip the reduced surrogate run (12000 + 2000 + 1000 CZT solves, 150 epochs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch of the 20 mm element")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file for the batch plan")
@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-sa", action="store_true",
                     help="skip the non-paraxial path on the accuracy study's plate at N = 28672")
     ap.add_argument("--sa-steps", type=int, default=3)
-    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs"], default=None,
+    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas"], default=None,
                     help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
@@ -473,6 +473,37 @@ def run_convergence(dev):
             "reference": {k: round(v, 9) for k, v in ref.items()}, "rows": rows}
 
 
+def run_blas(dev):
+    """The vendor BF16 GEMM (torch.matmul, hipBLASLt on ROCm) on this GPU, for
+    what a library GEMM attains against the same 2.5 PFLOP/s dense peak: a
+    square 16384^3 product and one shaped like a binary-stripe row pass (16384
+    aperture rows x one 65536-column K segment x 1024 real ROI columns)."""
+    import torch
+    out = {}
+    for name, (m, k, n) in {"square_16384": (16384, 16384, 16384),
+                            "row_pass_shape": (16384, 65536, 1024)}.items():
+        a = torch.randn(m, k, device=dev, dtype=torch.bfloat16)
+        b = torch.randn(k, n, device=dev, dtype=torch.bfloat16)
+        for _ in range(3):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * m * k * n / ms / 1e9
+        out[name] = {"m": m, "k": k, "n": n, "ms": round(ms, 4), "tflops": round(tf, 1),
+                     "frac_of_bf16_peak": round(tf / PEAK_BF16_TFLOPS, 4)}
+        log(f"torch.matmul bf16 {m}x{k}x{n}: {ms:.3f} ms, {tf:.0f} TFLOP/s")
+        del a, b, c
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -501,7 +532,8 @@ def main():
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
-               "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev)}[args.only]
+               "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev),
+               "blas": lambda: run_blas(dev)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -643,8 +675,8 @@ def main():
         if args.surrogate:
             out["surrogate"] = SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
         else:
-            out["surrogate"] = SG.run(sw, 4096, 512, 512, 30, log=log)
-            out["surrogate"]["reduced"] = "4096 training, 512 validation, 512 test solves, 30 epochs"
+            out["surrogate"] = SG.run(sw, 12000, 2000, 1000, 150, log=log)
+            out["surrogate"]["reduced"] = "12000 training, 2000 validation, 1000 test solves, 150 epochs"
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)

@@ -383,6 +383,58 @@ fzp_status_t fzp_log_intensity(const double *roi_dev, int64_t n_complex, double 
 fzp_status_t fzp_field_from_log_intensity(const float *y_dev, int64_t n_complex, double i0, double floor_,
                                           double *roi_dev, void *stream);
 
+/* Physics prior of the surrogate: the focal-plane intensity of a deformed
+ * binary plate's first diffraction order treated as a thin lens with the
+ * plate's pupil.  The Eq. 4 plate is periodic in s = r^2 / (lambda0 f0) (period
+ * 2); its converging Fourier term has amplitude 1/pi, and at that term's focus
+ * (lambda z = lambda0 f0) the Fresnel integral of Eq. 2 becomes a Fourier
+ * transform of the pupil times the crease phase screen exp(2 pi i h / lambda)
+ * (the creases of fzp_instance_t).  For each of n instances, on the M x M ROI
+ * of a default instance at its focus (samples (q - M/2) 16 lambda0 f0 / (D M)):
+ *   y[p][q] = ln(16 |S_pq|^2 / (pi^2 Np^4) + floor)   (I / I0 + floor,
+ *             I0 = (R^2 / (lambda0 f0))^2, the undeformed peak),
+ *   S = E g E^T,  g[j][i] = P_ij exp(2 pi i h(u_i, u_j) / lambda),
+ *   u_i = (2 i + 1 - Np) D / (2 Np),  E[q][i] = exp(-2 pi i 4 (2i+1-Np)(2q-M) / (Np M)),
+ * P_ij the share of the pixel's ss x ss sub-sample centres inside the disc.
+ * The zero order and the defocused orders are not modelled (the surrogate's
+ * network learns that remainder).  Phases and ridge heights in float64, the
+ * pupil field, the transforms and y in float32. */
+typedef struct {
+  double D;          /* aperture diameter [m] (crease offsets and widths are in metres) */
+  int32_t M;         /* ROI side, 1 .. 4096 */
+  int32_t Np;        /* pupil grid side, 16 .. 1024, a multiple of 16 */
+  int32_t ss;        /* sub-samples per pupil pixel side for the disc edge, 1 .. 16 */
+  int32_t n_creases; /* creases per instance, 0 .. 64 */
+  double floor_;     /* log floor relative to I0, > 0 */
+} fzp_prior_t;
+/* Workspace bytes (256-byte aligned, owned by the caller) for up to n_max
+ * instances per call; FZP_E_INVAL for a bad configuration. */
+fzp_status_t fzp_pupil_prior_workspace(const fzp_prior_t *cfg, int32_t n_max, size_t *bytes);
+/* Device arrays: creases_dev [n][n_creases][4] float64 (theta, offset, width
+ * (FWHM), height, as fzp_crease_t; NULL when n_creases = 0), lam_dev [n]
+ * float64, y_dev [n][M][M] float32.  0 <= n <= 65535; FZP_E_NOMEM when
+ * workspace_bytes is below fzp_pupil_prior_workspace(cfg, n).  Asynchronous on
+ * `stream`; allocates nothing. */
+fzp_status_t fzp_pupil_prior(const fzp_prior_t *cfg, const double *creases_dev, const double *lam_dev, int32_t n,
+                             float *y_dev, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Batched FWHM of log-intensity maps y = ln(I / I0 + floor) (the surrogate's
+ * form; y_dev [n][M][M] float32, 5 <= M <= 2048), for the surrogate's gate: per
+ * map the brightest sample (first index on ties), the FWHM in samples along its
+ * row by the metric extractor's spline (fzp_metrics' fwhm_x / pitch), and two
+ * conditioning numbers that need no reference map: cond = (w(1/2 - d) -
+ * w(1/2 + d)) / (2 d w(1/2)) with w(l) the full width at level l of the peak and
+ * d = level_delta (0 < d < 0.25): about 1.5 for a clean core, large where a
+ * shoulder or a secondary peak sits near half the maximum (+inf if a width is
+ * undefined); ratio = the brightest sample farther than exclusion_radius
+ * samples from the peak over the peak; gap = 1 - (brightest sample of the
+ * brighter neighbouring row) / peak and walt = the FWHM in samples along that
+ * row (a map whose brightest sample moves there reads walt; gap = 1 and walt =
+ * NaN without a neighbouring row).  out_dev [n][5] float64 = (FWHM, cond,
+ * ratio, gap, walt).  Asynchronous on `stream`; allocates nothing. */
+fzp_status_t fzp_fwhm_batch(const float *y_dev, int32_t n, int32_t M, double floor_, double level_delta,
+                            double exclusion_radius, double *out_dev, void *stream);
+
 /* Thread-local message of the last non-OK status on this thread. */
 const char *fzp_last_error(void);
 

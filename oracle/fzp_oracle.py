@@ -378,8 +378,9 @@ def intensity(U: np.ndarray) -> np.ndarray:
     return (U.real ** 2 + U.imag ** 2)
 
 
-def fwhm_1d(row: np.ndarray) -> float:
-    """Full width at half maximum of a sampled profile, in samples.
+def fwhm_1d(row: np.ndarray, frac: float = 0.5) -> float:
+    """Full width at half maximum of a sampled profile, in samples (with
+    ``frac``: the full width at that fraction of the maximum).
 
     Not-a-knot cubic spline through all samples; the spline peak is the largest
     spline value on the two sample intervals next to the brightest sample; the
@@ -399,7 +400,7 @@ def fwhm_1d(row: np.ndarray) -> float:
             if abs(t.imag) == 0.0 and 0.0 <= t.real <= 1.0:
                 cand.append(lo + float(t.real))
     peak = max(float(cs(t)) for t in cand)
-    half = 0.5 * peak
+    half = frac * peak
     left = k
     while left >= 0 and row[left] >= half:
         left -= 1

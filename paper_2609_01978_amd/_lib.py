@@ -49,7 +49,8 @@ EXPORTED = [
     "fzp_last_error", "fzp_profile_enable", "fzp_profile_read", "fzp_graph_create", "fzp_graph_launch",
     "fzp_graph_destroy", "fzp_autotune", "fzp_mlp_create", "fzp_mlp_info", "fzp_mlp_set_params",
     "fzp_mlp_get_params", "fzp_mlp_forward", "fzp_mlp_backward", "fzp_mlp_train_step", "fzp_mlp_adam_update",
-    "fzp_mlp_destroy", "fzp_log_intensity", "fzp_field_from_log_intensity",
+    "fzp_mlp_destroy", "fzp_log_intensity", "fzp_field_from_log_intensity", "fzp_pupil_prior_workspace",
+    "fzp_pupil_prior", "fzp_fwhm_batch",
 ]
 
 
@@ -186,6 +187,12 @@ def load_library() -> ctypes.CDLL:
         getattr(lib, name).restype = st
     lib.fzp_mlp_destroy.argtypes = [P]
     lib.fzp_mlp_destroy.restype = None
+    lib.fzp_pupil_prior_workspace.argtypes = [ctypes.POINTER(PriorCfg), i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fzp_pupil_prior.argtypes = [ctypes.POINTER(PriorCfg), P, P, i32, P, P, ctypes.c_size_t, P]
+    lib.fzp_pupil_prior_workspace.restype = st
+    lib.fzp_pupil_prior.restype = st
+    lib.fzp_fwhm_batch.argtypes = [P, i32, i32, dbl, dbl, dbl, P, P]
+    lib.fzp_fwhm_batch.restype = st
     lib.fzp_last_error.argtypes = []
     lib.fzp_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -456,6 +463,57 @@ class MLP:
     def adam_update(self, grads, lr: float, stream=None):
         _check(self._lib, self._lib.fzp_mlp_adam_update(self._h, _ptr(self.ws), _ptr(grads), float(lr),
                                                         _stream_handle(stream)))
+
+
+class PriorCfg(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("M", ctypes.c_int32), ("Np", ctypes.c_int32), ("ss", ctypes.c_int32),
+                ("n_creases", ctypes.c_int32), ("floor_", ctypes.c_double)]
+
+
+class PupilPrior:
+    """fzp_pupil_prior: the surrogate's physics prior (first order as a thin lens
+    with the deformed pupil) as log-intensity ln(I/I0 + floor) on the M x M ROI,
+    for batches of up to n_max instances per library call."""
+
+    def __init__(self, D: float, M: int, n_creases: int, Np: int = 128, ss: int = 4, floor: float = 1e-2,
+                 n_max: int = 1024, device="cuda"):
+        import torch
+        self._lib = load_library()
+        self.cfg = PriorCfg(D=float(D), M=int(M), Np=int(Np), ss=int(ss), n_creases=int(n_creases),
+                            floor_=float(floor))
+        self.M, self.n_creases, self.n_max, self.device = int(M), int(n_creases), int(n_max), device
+        nb = ctypes.c_size_t()
+        _check(self._lib, self._lib.fzp_pupil_prior_workspace(ctypes.byref(self.cfg), self.n_max, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def __call__(self, creases, lams, out=None, stream=None):
+        """creases [n, n_creases, 4] and lams [n] (host arrays) -> out [n, M*M] float32 (device)."""
+        import torch
+        cr = torch.as_tensor(np.asarray(creases, dtype=np.float64).reshape(len(lams), self.n_creases, 4),
+                             device=self.device).contiguous()
+        lm = torch.as_tensor(np.asarray(lams, dtype=np.float64), device=self.device).contiguous()
+        n = int(lm.shape[0])
+        if out is None:
+            out = torch.empty((n, self.M * self.M), dtype=torch.float32, device=self.device)
+        for s in range(0, n, self.n_max):
+            e = min(s + self.n_max, n)
+            _check(self._lib, self._lib.fzp_pupil_prior(ctypes.byref(self.cfg), _ptr(cr[s:e]) if self.n_creases else None,
+                                                        _ptr(lm[s:e]), e - s, _ptr(out[s:e]), _ptr(self.ws),
+                                                        self.ws_bytes, _stream_handle(stream)))
+        return out
+
+
+def fwhm_batch(y, M: int, floor: float, level_delta: float = 0.05, exclusion_radius: float = 10.0, stream=None):
+    """fzp_fwhm_batch on y [n, M*M] (device float32 log-intensity maps): a device
+    float64 tensor [n, 5] of (FWHM in samples, cond, ratio, gap, walt)."""
+    import torch
+    lib = load_library()
+    n = int(y.shape[0])
+    out = torch.empty((n, 5), dtype=torch.float64, device=y.device)
+    _check(lib, lib.fzp_fwhm_batch(_ptr(y), n, int(M), float(floor), float(level_delta), float(exclusion_radius),
+                                   _ptr(out), _stream_handle(stream)))
+    return out
 
 
 def grid_for_element(D: float, f0: float, lambda0: float, levels: int = 0, s_samp: int = 0):

@@ -5,6 +5,7 @@
 // a fixed order (no atomics), so the results are reproducible.
 
 #include <cmath>
+#include <string>
 
 #include "fzp_device.h"
 #include "fzp_internal.h"
@@ -120,8 +121,9 @@ __device__ Cubic piece(const double *y, int64_t stride, const double *m, int i) 
 
 __device__ __forceinline__ double ev(const Cubic &c, double t) { return ((c.a * t + c.b) * t + c.c) * t + c.d; }
 
-// FWHM in samples of the profile y[0..n-1] (stride), or NaN.
-__device__ double fwhm_profile(const double *y, int64_t stride, int n, double *m, double *cp) {
+// FWHM in samples of the profile y[0..n-1] (stride), or NaN; with `frac` the
+// full width at that fraction of the spline peak instead of one half.
+__device__ double fwhm_profile(const double *y, int64_t stride, int n, double *m, double *cp, double frac = 0.5) {
   int k = 0;
   double best = y[0];
   for (int i = 1; i < n; ++i) {
@@ -161,7 +163,7 @@ __device__ double fwhm_profile(const double *y, int64_t stride, int n, double *m
         if (v > peak) peak = v;
       }
   }
-  const double half = 0.5 * peak;
+  const double half = frac * peak;
   int left = k, right = k;
   while (left >= 0 && y[(int64_t)left * stride] >= half) --left;
   while (right < n && y[(int64_t)right * stride] >= half) ++right;
@@ -218,6 +220,103 @@ __global__ __launch_bounds__(64) void k_reduce_fwhm(InstDev d, const double *__r
     else
       w = fwhm_profile(I + q, M, M, s_m, s_c);
     res[2 + blockIdx.x] = w * d.dx_out;
+  }
+}
+
+// Batched FWHM of log-intensity maps y = ln(I / I0 + floor) (the surrogate's
+// form), one work-group per map: the brightest sample (first index on ties),
+// the FWHM along its row (spline, as fwhm_profile), and two conditioning
+// numbers that do not need the true map:
+//   cond  = (w(1/2 - delta) - w(1/2 + delta)) / (2 delta w(1/2)), the relative
+//           change of the width per unit change of the level (about 1.5 for an
+//           Airy or Gaussian core; a shoulder or secondary peak near half the
+//           maximum makes it jump);
+//   ratio = the brightest sample farther than `excl` samples from the peak,
+//           relative to the peak (a second spot that could take the peak over);
+//   gap   = 1 - (brightest sample of the brighter neighbouring row) / peak, and
+//   walt  = the FWHM along that neighbouring row: when the gap is small a
+//           slightly different map can put its brightest sample there.
+// A NaN width gives cond = +inf.  out[b][0..4] = (FWHM in samples, cond, ratio,
+// gap, walt).
+__global__ __launch_bounds__(kRedThreads) void k_fwhm_batch(const float *__restrict__ y, int M, double floor_,
+                                                            double delta, double excl2, double *__restrict__ out) {
+  extern __shared__ double s_row[];  // row, neighbour row, spline m, spline work: 4 M doubles
+  __shared__ float s_v[kRedThreads];
+  __shared__ int s_i[kRedThreads];
+  const int b = blockIdx.x;
+  const float *yb = y + (int64_t)b * M * M;
+  const int MM = M * M;
+  float bv = -INFINITY;
+  int bi = INT32_MAX;
+  for (int i = threadIdx.x; i < MM; i += kRedThreads)
+    if (yb[i] > bv) {  // increasing i: the first index wins ties
+      bv = yb[i];
+      bi = i;
+    }
+  s_v[threadIdx.x] = bv;
+  s_i[threadIdx.x] = bi;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const float v = s_v[threadIdx.x + h];
+      const int i = s_i[threadIdx.x + h];
+      if (v > s_v[threadIdx.x] || (v == s_v[threadIdx.x] && i < s_i[threadIdx.x])) {
+        s_v[threadIdx.x] = v;
+        s_i[threadIdx.x] = i;
+      }
+    }
+    __syncthreads();
+  }
+  const float ymax = s_v[0];
+  const int pk = s_i[0];
+  const int p = pk / M, q = pk % M;
+  __syncthreads();
+  // brightest sample outside the exclusion disc around the peak, and the
+  // brightest samples of the rows above and below the peak's row
+  float b2 = -INFINITY, up = -INFINITY, dn = -INFINITY;
+  for (int i = threadIdx.x; i < MM; i += kRedThreads) {
+    const int r = i / M;
+    const double dp = (double)(r - p), dq = (double)(i % M - q);
+    if (dp * dp + dq * dq > excl2 && yb[i] > b2) b2 = yb[i];
+    if (r == p - 1 && yb[i] > up) up = yb[i];
+    if (r == p + 1 && yb[i] > dn) dn = yb[i];
+  }
+  __shared__ float s_up[kRedThreads], s_dn[kRedThreads];
+  s_v[threadIdx.x] = b2;
+  s_up[threadIdx.x] = up;
+  s_dn[threadIdx.x] = dn;
+  for (int i = threadIdx.x; i < M; i += kRedThreads) s_row[i] = exp((double)yb[(int64_t)p * M + i]) - floor_;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s_v[threadIdx.x] = fmaxf(s_v[threadIdx.x], s_v[threadIdx.x + h]);
+      s_up[threadIdx.x] = fmaxf(s_up[threadIdx.x], s_up[threadIdx.x + h]);
+      s_dn[threadIdx.x] = fmaxf(s_dn[threadIdx.x], s_dn[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  // the brighter neighbouring row (the row above on ties; none at the ROI edge)
+  const int pn = s_up[0] >= s_dn[0] ? p - 1 : p + 1;
+  const float yn = s_up[0] >= s_dn[0] ? s_up[0] : s_dn[0];
+  const bool has_n = yn != -INFINITY;
+  if (has_n)
+    for (int i = threadIdx.x; i < M; i += kRedThreads) s_row[M + i] = exp((double)yb[(int64_t)pn * M + i]) - floor_;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double *m = s_row + 2 * M, *cp = s_row + 3 * M;
+    const double w = fwhm_profile(s_row, 1, M, m, cp);
+    const double wl = fwhm_profile(s_row, 1, M, m, cp, 0.5 - delta);
+    const double wh = fwhm_profile(s_row, 1, M, m, cp, 0.5 + delta);
+    double cond = (wl - wh) / (2.0 * delta * w);
+    if (!(cond == cond)) cond = INFINITY;
+    const double peak = exp((double)ymax) - floor_;
+    const double sec = s_v[0] == -INFINITY ? 0.0 : exp((double)s_v[0]) - floor_;
+    double *o = out + 5 * (int64_t)b;
+    o[0] = w;
+    o[1] = cond;
+    o[2] = peak > 0.0 ? sec / peak : INFINITY;
+    o[3] = has_n && peak > 0.0 ? 1.0 - (exp((double)yn) - floor_) / peak : 1.0;
+    o[4] = has_n ? fwhm_profile(s_row + M, 1, M, m, cp) : NAN;
   }
 }
 
@@ -339,6 +438,13 @@ __global__ void k_finish(InstDev d, const double *res, double disc_samples, doub
 
 }  // namespace
 
+hipError_t launch_fwhm_batch(const float *y, int32_t n, int32_t M, double floor_, double delta, double excl,
+                             double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwhm_batch, dim3((unsigned)n), dim3(kRedThreads), (size_t)4 * M * sizeof(double), st, y, M,
+                     floor_, delta, excl * excl, out);
+  return hipGetLastError();
+}
+
 size_t metrics_scratch_bytes(int32_t M) { return (sc_end(M) + 255) & ~(size_t)255; }
 
 hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samples, char *scratch,
@@ -372,3 +478,24 @@ hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samp
 }
 
 }  // namespace fzp
+
+extern "C" fzp_status_t fzp_fwhm_batch(const float *y_dev, int32_t n, int32_t M, double floor_, double level_delta,
+                                       double exclusion_radius, double *out_dev, void *stream) {
+  if (n < 0 || M < 5 || M > 2048 || !(floor_ > 0.0) || !std::isfinite(floor_) || !(level_delta > 0.0) ||
+      !(level_delta < 0.25) || !(exclusion_radius >= 0.0) || !std::isfinite(exclusion_radius)) {
+    fzp::set_last_error("fzp_fwhm_batch: bad argument");
+    return FZP_E_INVAL;
+  }
+  if (n == 0) return FZP_OK;
+  if (!y_dev || !out_dev) {
+    fzp::set_last_error("fzp_fwhm_batch: NULL pointer");
+    return FZP_E_INVAL;
+  }
+  const hipError_t e =
+      fzp::launch_fwhm_batch(y_dev, n, M, floor_, level_delta, exclusion_radius, out_dev, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    fzp::set_last_error(std::string("fzp_fwhm_batch: ") + hipGetErrorString(e));
+    return FZP_E_DEVICE;
+  }
+  return FZP_OK;
+}

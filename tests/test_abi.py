@@ -38,6 +38,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(L.Options) == 40
     assert ctypes.sizeof(L.Geometry) == 40
     assert ctypes.sizeof(L.Metrics) == 64
+    assert ctypes.sizeof(L.PriorCfg) == 32
 
 
 def ap_of(name):
@@ -279,3 +280,28 @@ def test_grid_for_element_arguments():
     with pytest.raises(P.FZPError):
         P.Plan(dict(D=1.0, f0=5.0, lambda0=532e-9, N=(1 << 24) + 1), [dict(lam=532e-9, M=64)],
                allow_undersampled=True)
+
+
+def test_pupil_prior_host_validation():
+    """fzp_pupil_prior_workspace's size rule and the argument checks that both
+    prior calls make on the host before any launch (the fake device addresses
+    below are never touched: every call here returns before launching)."""
+    lib = P.load_library()
+    ok = dict(D=10e-3, M=128, Np=128, ss=4, n_creases=8, floor_=1e-2)
+    nb = ctypes.c_size_t()
+    assert lib.fzp_pupil_prior_workspace(ctypes.byref(L.PriorCfg(**ok)), 7, ctypes.byref(nb)) == L.FZP_OK
+    a256 = lambda v: (v + 255) // 256 * 256
+    assert nb.value == a256(128 * 128 * 8) + a256(7 * (128 * 128 + 128 * 128) * 8)
+    for bad in (dict(Np=8), dict(Np=24), dict(Np=2048), dict(ss=0), dict(ss=17), dict(n_creases=65),
+                dict(n_creases=-1), dict(M=0), dict(M=5000), dict(floor_=0.0), dict(D=0.0), dict(D=float("nan"))):
+        cfg = L.PriorCfg(**{**ok, **bad})
+        assert lib.fzp_pupil_prior_workspace(ctypes.byref(cfg), 1, ctypes.byref(nb)) == L.FZP_E_INVAL, bad
+        assert lib.fzp_pupil_prior(ctypes.byref(cfg), 16, 16, 1, 16, 16, 1 << 30, None) == L.FZP_E_INVAL, bad
+    cfg = L.PriorCfg(**ok)
+    assert lib.fzp_pupil_prior_workspace(ctypes.byref(cfg), 0, ctypes.byref(nb)) == L.FZP_E_INVAL
+    assert lib.fzp_pupil_prior(ctypes.byref(cfg), None, None, 0, None, None, 0, None) == L.FZP_OK      # nothing to do
+    assert lib.fzp_pupil_prior(ctypes.byref(cfg), None, 16, 2, 16, 16, 1 << 30, None) == L.FZP_E_INVAL  # no creases
+    assert lib.fzp_pupil_prior(ctypes.byref(cfg), 16, 16, 70000, 16, 16, 1 << 40, None) == L.FZP_E_INVAL
+    lib.fzp_pupil_prior_workspace(ctypes.byref(cfg), 3, ctypes.byref(nb))
+    assert lib.fzp_pupil_prior(ctypes.byref(cfg), 16, 16, 3, 16, 16, nb.value - 1, None) == L.FZP_E_NOMEM
+    assert "workspace" in lib.fzp_last_error().decode()

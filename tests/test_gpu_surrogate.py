@@ -1,7 +1,9 @@
 """GPU: the learned surrogate end to end at the surrogate workload's aperture
 (D = 10 mm, f/5, N = 16384, ROI 128^2) on a reduced data set: CZT targets,
-training by the library's kernels, the calibrated ensemble gate, the CZT
-fallback, and what the network gains over solving every case by CZT.
+the physics prior (fzp_pupil_prior), training of the residual network by the
+library's kernels, the calibrated ensemble gate with its conditioning checks
+(fzp_fwhm_batch), the CZT fallback, and what the trained surrogate gains over
+solving every case by CZT.
 """
 import time
 
@@ -10,9 +12,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-import paper_2609_01978_amd as P  # noqa: E402
 from paper_2609_01978_amd import surrogate as SG  # noqa: E402
-from oracle import fzp_oracle as O  # noqa: E402
 from fzp_inputs import surrogate_draws, workload  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -37,81 +37,49 @@ def test_targets_match_fp64_path():
 
 
 @pytest.fixture(scope="module")
-def trained():
-    """CZT data of the surrogate aperture (4096 training, 512 validation and 512
-    test solves), a two-member ensemble trained by the library's kernels, and its
-    gate calibrated on the validation solves."""
+def report():
+    """SG.run on 12000 training, 2000 validation and 1000 test CZT solves,
+    150 epochs: the prior, the residual ensemble, the gate calibrated on the
+    validation solves, and the test-set report."""
     w = workload("surrogate")
-    n_tr, n_val, n_te = 4096, 512, 512
-    cr_tr, lam_tr = surrogate_draws(w["train_seed"], n_tr + n_val, w["D"], w["lambda0"])
-    cr_te, lam_te = surrogate_draws(w["test_seed"], n_te, w["D"], w["lambda0"])
-    solver = SG.CZTSolver(w)
-    t_all, sec_all = solver.solve(cr_tr, lam_tr)
-    t_te, sec_te = solver.solve(cr_te, lam_te)
-    czt_per_case = (sec_all + sec_te) / (n_tr + n_val + n_te)
-    announce(f"CZT data: {n_tr + n_val + n_te} solves, {czt_per_case * 1e3:.2f} ms per solve")
-    f_all = SG.features(cr_tr, lam_tr, w["D"], w["lambda0"])
-    f_te = SG.features(cr_te, lam_te, w["D"], w["lambda0"])
-    x_all = torch.from_numpy(f_all).cuda()
-    x_te = torch.from_numpy(f_te).cuda()
-    S = SG.Surrogate(w)
-    S.init(t_sample=t_all[:1024])
     t0 = time.perf_counter()
-    losses = S.fit(x_all[:n_tr], t_all[:n_tr], epochs=30, log=None)
-    torch.cuda.synchronize()
-    announce(f"training 2 x 30 epochs: {time.perf_counter() - t0:.1f} s, loss {losses[0][0]:.4f} -> "
-             f"{losses[0][-1]:.4f} / {losses[1][0]:.4f} -> {losses[1][-1]:.4f}")
-    fw_val = S.reader.fwhm(t_all[n_tr:])
-    cal = S.calibrate(x_all[n_tr:], fw_val, f_all[n_tr:])
-    announce(f"gate calibration on validation: {cal}")
-    fw_te = S.reader.fwhm(t_te)
-    acc, y, f_pred, dis = S.accept(x_te, f_te)
-    err = np.abs(f_pred / fw_te - 1.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        S.predict(x_te)
-    torch.cuda.synchronize()
-    net_per_case = (time.perf_counter() - t0) / (3 * n_te)   # both members
-    frac = float(acc.mean())
-    mixed = net_per_case + (1.0 - frac) * czt_per_case
-    announce(f"test: accepted {frac * 100:.1f} %, FWHM error accepted max "
-             f"{(err[acc].max() if acc.any() else 0) * 100:.3f} %, all cases median {np.median(err) * 100:.3f} %; "
-             f"network {net_per_case * 1e6:.1f} us per case vs CZT {czt_per_case * 1e3:.2f} ms; "
-             f"gain with fallback x{czt_per_case / mixed:.3f}")
-    return dict(w=w, S=S, solver=solver, losses=losses, cal=cal, acc=acc, err=err, frac=frac,
-                cr_te=cr_te, f_te=f_te, czt_per_case=czt_per_case, net_per_case=net_per_case,
-                gain=czt_per_case / mixed)
+    r = SG.run(w, 12000, 2000, 1000, 150, log=lambda m: announce(m) if ("gate" in m or "CZT" in m) else None)
+    announce(f"run: {time.perf_counter() - t0:.1f} s; " + ", ".join(f"{k} {v}" for k, v in r.items()))
+    return r
 
 
-def test_surrogate_trains_and_gate_is_calibrated(trained):
-    """Training reduces both members' loss; the calibrated gate keeps every
-    accepted validation case within the FWHM target; an input outside the
-    training box is never accepted and the CZT answers it."""
-    for ls in trained["losses"]:
-        assert ls[-1] < 0.95 * ls[0]
-    assert trained["cal"]["max_err_accepted"] <= 0.005
-    assert 0.0 <= trained["cal"]["tau"] <= 0.0025
-    S, w = trained["S"], trained["w"]
-    cr_out, lam_out = trained["cr_te"][:4].copy(), np.full(4, 900e-9)
-    f_out = SG.features(cr_out, lam_out, w["D"], w["lambda0"])
-    acc_out, _, _, _ = S.accept(torch.from_numpy(f_out).cuda(), f_out)
-    assert not acc_out.any()
-    t_out, _ = trained["solver"].solve(cr_out, lam_out)
+def test_prior_and_gate(report):
+    """The prior alone reads the FWHM within the target for most held-out
+    cases, and the gate calibrates to a positive threshold."""
+    assert report["prior_frac_within_target"] >= 0.95
+    assert report["gate_tau"] > 0.0
+
+
+def test_network_improves_on_the_prior(report):
+    """What the trained network adds to the physics prior on the held-out
+    cases: a smaller median FWHM error and a smaller median ROI intensity
+    error than the prior alone."""
+    assert report["fwhm_err_all_median"] < report["prior_fwhm_err_median"]
+    assert report["roi_rel_l2_median"] < report["prior_roi_rel_l2_median"]
+
+
+def test_surrogate_gains_over_czt(report):
+    """What the trained surrogate gains over solving every case by CZT: a share
+    of the held-out cases accepted, each within 0.5 % of the CZT's FWHM, and an
+    end-to-end speed-up that counts the prior, both members, the gate's FWHM
+    readings and the fallback solves."""
+    assert report["accepted_fraction"] >= 0.2
+    assert report["fwhm_err_accepted_max"] <= 0.005
+    assert report["speedup_with_fallback"] > 1.2
+    assert report["speedup_accepted"] > 20
+
+
+def test_out_of_box_input_is_never_accepted():
+    """A wavelength outside the training range is rejected before any network
+    evaluation, and the CZT answers it."""
+    w = workload("surrogate")
+    cr, _ = surrogate_draws(5, 4, w["D"], w["lambda0"])
+    f_out = SG.features(cr, np.full(4, 900e-9), w["D"], w["lambda0"])
+    assert not SG.in_training_box(f_out).any()
+    t_out, _ = SG.CZTSolver(w).solve(cr, np.full(4, 900e-9))
     assert torch.isfinite(t_out).all()
-    # one network evaluation (both members) costs far less than one CZT solve:
-    # the gain available to an accepted case
-    assert trained["czt_per_case"] / trained["net_per_case"] > 20
-
-
-@pytest.mark.xfail(strict=True, reason=(
-    "measured: at the configured deformations (8 creases up to lambda0/2) the gate accepts no test "
-    "case (the network's FWHM error, median ~9 %, does not beat a constant prediction), so every case "
-    "falls back to the CZT and the gain with fallback is x1.0"))
-def test_surrogate_gains_over_czt(trained):
-    """What the trained network gains over solving every case by CZT: a share of
-    the held-out cases accepted, each within 0.5 % of the CZT's FWHM, and an
-    end-to-end speed-up that includes the fallback solves."""
-    assert trained["frac"] >= 0.05
-    assert trained["err"][trained["acc"]].max() <= 0.005
-    assert trained["gain"] > 1.05
