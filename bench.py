@@ -608,6 +608,9 @@ def main():
                     frac=round(achieved / PEAK_BF16_TFLOPS, 4), traffic=traffic,
                     traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     mfma_busy=mfma_busy,
+                    committed_from=("profiles/hbm_traffic_k_row_pass_split_fzp1m.md (traffic), "
+                                    "profiles/sq_counters_k_row_pass_split_fzp1m.md (mfma_busy): rocprofv3 "
+                                    "counter runs of the same sources, not this run"),
                     kernel="k_row_pass_split",
                     launch_ms=round(pr["row_ms"] / max(pr["row_launches"], 1), 3),
                     launches_per_step=launches_per_step,

@@ -100,6 +100,11 @@ typedef int32_t fzp_status_t;
 #define FZP_FLAG_BIN_PREFETCH 8       /* variant 3: variant 2 reading the next stage's first
                                          operand fragments one stage early */
 #define FZP_FLAG_BIN_DEEP 32          /* variant 2: 512-row tile with an 8-stage LDS pipeline */
+#define FZP_FLAG_CPLX_TILE_128 128    /* split path, complex stripes: start with the 128-column GEMM
+                                         tile instead of the 256-column one (same results bit for
+                                         bit; fzp_autotune may change it) */
+#define FZP_FLAG_CPLX_TILE_DUAL 256   /* as FZP_FLAG_CPLX_TILE_128 with a 2-stage LDS ring and two
+                                         work-groups per compute unit */
 #define FZP_FLAG_PARAXIAL_RADII 64    /* FZP_PATH_SA_CZT: the paraxial radii of Eq. 4 (r_n^2 = n
                                          lambda0 f0) instead of Eq. 3, e.g. to compare with the
                                          Fresnel paths */
@@ -315,7 +320,11 @@ void fzp_graph_destroy(fzp_graph_t g);
  * 1: 256-row tile, two work-groups per compute unit; 2: 512-row tile with an
  * 8-stage pipeline; 3: variant 2 with the next stage's first operand fragments
  * read one stage early; 4: variant 2 with the mask expansion interleaved with the
- * MFMAs), and the number of concurrent lanes (1 .. options.lanes).  Each candidate runs one
+ * MFMAs), for complex stripes the GEMM tile (256 or 128 real columns, the latter
+ * also with two work-groups per compute unit), and the
+ * number of concurrent lanes (1 .. options.lanes).  The variant reported and
+ * cached is the binary variant + 8 x the complex tile (0: 256, 1: 128, 2: 128 with
+ * two work-groups per compute unit).  Each candidate runs one
  * full propagation on `stream`, timed with HIP events; the fastest is kept in
  * the plan.  With a non-NULL `cache_path` the choice is looked up first in
  * that text file (one "key seg_len lanes variant" line per plan shape and

@@ -22,8 +22,10 @@ constexpr int kCThreads = 512;
 // stage's), then barrier: N = 6 with all four stripe planes, 4 with the hi
 // planes only.
 template <int N> __device__ __forceinline__ void stage_barrier() {
-  static_assert(N == 6, "add the count");
-  asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  static_assert(N == 0 || N == 5 || N == 6, "add the count");
+  if constexpr (N == 6) asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 5) asm volatile("s_waitcnt vmcnt(5) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -46,7 +48,7 @@ template <int N> __device__ __forceinline__ void stage_barrier() {
 // tile, so one pipeline stage of a row tile is a contiguous 8 KiB per plane.
 // ---------------------------------------------------------------------------
 constexpr int kCTR = 256;     // rows per tile
-constexpr int kCTC = 256;     // real columns per tile (128 complex ROI columns)
+constexpr int kCTC = 256;     // real columns per tile (128 complex ROI columns); 128 in the narrow variant
 constexpr int kCKT = 16;      // K columns per pipeline stage (one MFMA K-step)
 constexpr int kCRowB = 32;    // LDS bytes per slab row
 constexpr int kCGBytes = 4 * kCTR * kCRowB;   // 32768: four stripe planes
@@ -54,6 +56,8 @@ constexpr int kCBBytes = 2 * kCTC * kCRowB;   // 16384: table hi and lo
 constexpr int kCStage = kCGBytes + kCBBytes;  // 49152
 constexpr int kCRing = 3, kCAhead = 2;
 constexpr int kCLdsBytes = kCRing * kCStage;  // 147456
+// LDS of a tile with CT real columns and a ring of RING stages
+constexpr int cplx_lds_bytes(int CT, int RING = kCRing) { return RING * (kCGBytes + 2 * CT * kCRowB); }
 
 // 16-byte half of a 32-byte slab row in LDS: swapped on rows 8..15 of every
 // 16 so that 16 consecutive rows read at one half hit 64 distinct banks.
@@ -225,8 +229,11 @@ __device__ __forceinline__ bf16x8 swap_neg(bf16x8 b, uint32_t nmask) {
 // (128 float32 accumulators per lane), 6 MFMAs per block per K-step.  Stripe
 // and table slabs move HBM -> LDS by direct copies into a 3-deep ring, 2
 // stages ahead, one barrier per stage.
-template <bool COL>
-__global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
+// CT = 128 with RING = 2 (one stage ahead, 80 KiB of LDS) fits two
+// work-groups per CU, so that one work-group's barrier waits are covered by
+// the other's MFMAs.
+template <bool COL, int CT = kCTC, int RING = kCRing>
+__global__ __launch_bounds__(kCThreads, RING == 2 ? 2 : 1) void k_row_pass_split_cplx(
     InstDev d, int64_t row_begin, int64_t row_end, int n_rt, int n_ct, int seg_lo, int n_seg,
     const uint16_t *__restrict__ G, int64_t rows_pad, int64_t kb0, int64_t nkb, float *__restrict__ T,
     int64_t seg_stride_f, const uint16_t *__restrict__ Bop, int64_t kB0, int64_t KB, int64_t k_begin, int64_t k_end,
@@ -247,7 +254,17 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   const int64_t r0 = row_begin + (int64_t)rt * kCTR;
   int64_t rl = r0 + kCTR - 1;
   if (rl > row_end - 1) rl = row_end - 1;
-  const int c0 = ct * kCTC;
+  // CT real columns per tile: waves 4 (rows) x 2 (columns), each CB column
+  // blocks of 32; NB table pieces (32 columns of one plane) copied per wave
+  static_assert(CT == 256 || CT == 128, "tile width");
+  static_assert(RING == 3 || RING == 2, "ring depth");
+  constexpr int CB = CT / 64, NB = CT / 128, PPP = CT / 32;
+  constexpr int kStage = kCGBytes + 2 * CT * kCRowB;
+  constexpr int kAheadR = RING - 1;
+  // copies a wave may leave in flight at a stage's end: those of the newest
+  // stage with two stages ahead, none with one
+  constexpr int kWait = RING == 3 ? 4 + NB : 0;
+  const int c0 = ct * CT;
   int64_t k_lo, k_hi;
   if constexpr (COL) {
     k_lo = k_begin + (int64_t)(seg - seg_lo) * seg_len_c;
@@ -280,13 +297,13 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
     const int row = (x & 7) * 32 + (lane >> 1);
     gsrc[j] = G + (x >> 3) * plane + ((int64_t)rt * kCTR + row) * 16 + 8 * chalf(row, lane & 1);
   }
-  const uint16_t *bsrc[2];
+  const uint16_t *bsrc[NB];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int y = 2 * wave + j;
-    const int col = (y & 7) * 32 + (lane >> 1);
+  for (int j = 0; j < NB; ++j) {
+    const int y = NB * wave + j;
+    const int col = (y % PPP) * 32 + (lane >> 1);
     const int gc = c0 + col < M2 ? c0 + col : 0;
-    bsrc[j] = Bop + (int64_t)(y >> 3) * M2 * KB + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
+    bsrc[j] = Bop + (int64_t)(y / PPP) * M2 * KB + (int64_t)gc * 32 + 8 * chalf(col, lane & 1);
   }
 
   // ---- compute role: wave (wr, wc) covers rows wr*64 .., columns wc*128 ..
@@ -296,14 +313,14 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   const int l32 = lane & 31, lhi = lane >> 5;
   const int hofs = chalf(l32, lhi) * 16;
   const int aoff = (wr * 64 + l32) * kCRowB + hofs;
-  const int boff = kCGBytes + (wc * 128 + l32) * kCRowB + hofs;
+  const int boff = kCGBytes + (wc * 32 * CB + l32) * kCRowB + hofs;
   const uint32_t nmask = (lane & 1) ? 0u : 0x80008000u;
 
-  f32x16 acc[2][4];
+  f32x16 acc[2][CB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < CB; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
     const int64_t klast = k_hi - kCKT;  // copies past the end repeat the last stage
     auto copy_stage = [&](int s) {
       const int64_t k = kb + (int64_t)s * kCKT < klast ? kb + (int64_t)s * kCKT : klast;
-      char *dst = lds + (s % kCRing) * kCStage;
+      char *dst = lds + (s % RING) * kStage;
       const int64_t gofs = (k / 16 - kb0) * rows_pad * 16;
 #pragma unroll
       for (int j = 0; j < NG; ++j)
@@ -322,22 +339,22 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
       const int64_t kr = k - kB0;  // K index of the B operand's blocked layout
       const int64_t bofs = (kr >> 5) * M2 * 32 + (kr & 31);
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NB; ++j)
         __builtin_amdgcn_global_load_lds((const void *)(bsrc[j] + bofs),
                                          (__attribute__((address_space(3))) void *)(dst + kCGBytes +
-                                                                                    (2 * wave + j) * 1024),
+                                                                                    (NB * wave + j) * 1024),
                                          16, 0, 0);
     };
-    for (int s = 0; s < kCAhead; ++s) copy_stage(s);
-    stage_barrier<NG + 2>();
+    for (int s = 0; s < kAheadR; ++s) copy_stage(s);
+    stage_barrier<kWait>();
     for (int s = 0; s < nst; ++s) {
-      copy_stage(s + kCAhead);
-      const char *sb = lds + (s % kCRing) * kCStage;
-      bf16x8 bh[4], bl[4], bhs[4], bls[4];
+      copy_stage(s + kAheadR);
+      const char *sb = lds + (s % RING) * kStage;
+      bf16x8 bh[CB], bl[CB], bhs[CB], bls[CB];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < CB; ++cb) {
         bh[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB));
-        bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB + kCTC * kCRowB));
+        bl[cb] = __builtin_bit_cast(bf16x8, lds_ld16(sb + boff + cb * 32 * kCRowB + CT * kCRowB));
         bhs[cb] = swap_neg(bh[cb], nmask);
         bls[cb] = swap_neg(bl[cb], nmask);
       }
@@ -347,24 +364,24 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
         const bf16x8 rh = __builtin_bit_cast(bf16x8, lds_ld16(pa));
         const bf16x8 ih = __builtin_bit_cast(bf16x8, lds_ld16(pa + 2 * kCTR * kCRowB));
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bh[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bhs[cb], acc[rb][cb], 0, 0, 0);
         }
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bls[cb], acc[rb][cb], 0, 0, 0);
         }
         const bf16x8 rlo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 1 * kCTR * kCRowB));
         const bf16x8 ilo = __builtin_bit_cast(bf16x8, lds_ld16(pa + 3 * kCTR * kCRowB));
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rlo, bh[cb], acc[rb][cb], 0, 0, 0);
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ilo, bhs[cb], acc[rb][cb], 0, 0, 0);
         }
       }
-      stage_barrier<NG + 2>();
+      stage_barrier<kWait>();
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
@@ -375,8 +392,8 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
   if constexpr (COL) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int c = c0 + wc * 128 + cb * 32 + l32;
+    for (int cb = 0; cb < CB; ++cb) {
+      const int c = c0 + wc * 32 * CB + cb * 32 + l32;
       if (c >= M2) continue;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
@@ -392,8 +409,8 @@ __global__ __launch_bounds__(kCThreads, 1) void k_row_pass_split_cplx(
   }
   const int64_t rs = seg_stride_f / M2;
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    const int c = c0 + wc * 128 + cb * 32 + l32;
+  for (int cb = 0; cb < CB; ++cb) {
+    const int c = c0 + wc * 32 * CB + cb * 32 + l32;
     if (c >= M2) continue;
     float *col = Ts + (int64_t)c * rs - row_begin;
 #pragma unroll
@@ -551,6 +568,12 @@ hipError_t init_cplx_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kCLdsBytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<false, 128>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, cplx_lds_bytes(128));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_split_cplx<false, 128, 2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, cplx_lds_bytes(128, 2));
   return e;
 }
 
@@ -597,16 +620,30 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
   int seg_lo, seg_hi;
   split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
   if (seg_hi <= seg_lo || nkb <= 0) return hipSuccess;
+  // tile width: 256 real columns, or 128 (cplx_tile = 1: twice the work-groups
+  // for a small ROI, each operand read from LDS feeding half as many MFMAs;
+  // cplx_tile = 2: the same with a 2-stage ring and two work-groups per CU)
+  const int CT = d.cplx_tile >= 1 ? 128 : kCTC;
   const int n_rt = (int)((rows + kCTR - 1) / kCTR);
-  const int n_ct = (2 * d.M + kCTC - 1) / kCTC;
+  const int n_ct = (2 * d.M + CT - 1) / CT;
   const int n_seg = seg_hi - seg_lo;
   const int64_t Gn = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (Gn + 255) / 256 * 256;
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
-                     row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
-                     2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  if (d.cplx_tile == 2)
+    hipLaunchKernelGGL((k_row_pass_split_cplx<false, 128, 2>), dim3((unsigned)grid), dim3(kCThreads),
+                       cplx_lds_bytes(128, 2), st, d, row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad,
+                       kb0, nkb, (float *)T, 2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0,
+                       (int64_t)0);
+  else if (CT == 128)
+    hipLaunchKernelGGL((k_row_pass_split_cplx<false, 128>), dim3((unsigned)grid), dim3(kCThreads),
+                       cplx_lds_bytes(128), st, d, row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0,
+                       nkb, (float *)T, 2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
+  else
+    hipLaunchKernelGGL(k_row_pass_split_cplx<false>, dim3((unsigned)grid), dim3(kCThreads), kCLdsBytes, st, d,
+                       row_begin, row_end, n_rt, n_ct, seg_lo, n_seg, G, rows_pad, kb0, nkb, (float *)T,
+                       2 * seg_stride, d.A, (int64_t)0, d.Npad, (int64_t)0, (int64_t)0, (int64_t)0);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ struct InstDev {
   int32_t bin_tile_rows;   // split path, binary stripes: GEMM tile rows (512 or 256)
   int32_t bin_ring;        // split path, binary stripes, 512-row tile: LDS pipeline stages (4 or 8)
   int32_t bin_prefetch;    // 8-stage variant: 1 next-stage operands one stage early, 2 interleaved expansion
+  int32_t cplx_tile;       // split path, complex stripes: 0 the 256-column GEMM tile, 1 the 128-column tile,
+                           // 2 the 128-column tile with a 2-stage ring, two work-groups per CU
   int32_t levels;          // 0: binary amplitude plate; L >= 2: L-level phase plate
   double kappa_l;          // phase plates: kappa * (L / 2); level = floor(K kappa_l) mod L
 };
@@ -122,6 +124,7 @@ struct Plan {
   std::vector<size_t> off_T, off_bits, off_G, off_Tb, off_C;
   int32_t lanes_max = 1, lanes = 1;
   int64_t seg_len = 0;  // split path K segment (all instances)
+  int32_t cplx_variant = 0;  // split path complex-stripe GEMM tile (InstDev::cplx_tile)
   int32_t bin_variant = 4;  // split path binary-stripe GEMM: 0 512 rows, 1 256 rows, 2 512 rows deep ring,
                             // 3 deep ring with next-stage fragment prefetch, 4 deep ring interleaved
   std::vector<hipStream_t> lane_st;

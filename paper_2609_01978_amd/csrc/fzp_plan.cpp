@@ -87,13 +87,18 @@ hipError_t take_events(fzp::Plan &p, hipEvent_t &a, hipEvent_t &b, size_t &first
   return hipSuccess;
 }
 
-// Binary-stripe GEMM variant into every instance's kernel parameters.
+// GEMM variant into every instance's kernel parameters: v % 8 the
+// binary-stripe variant (0 .. 4), v / 8 the complex-stripe tile (0: 256
+// columns, 1: 128 columns, 2: 128 columns with two work-groups per CU).
 void set_variant(fzp::Plan &p, int32_t v) {
-  p.bin_variant = v;
+  const int32_t b = v % 8, c = v / 8;
+  p.bin_variant = b;
+  p.cplx_variant = c;
   for (auto &ih : p.inst) {
-    ih.dev.bin_tile_rows = v == 1 ? 256 : 512;
-    ih.dev.bin_ring = v >= 2 ? 8 : 4;
-    ih.dev.bin_prefetch = v == 3 ? 1 : (v == 4 ? 2 : 0);
+    ih.dev.bin_tile_rows = b == 1 ? 256 : 512;
+    ih.dev.bin_ring = b >= 2 ? 8 : 4;
+    ih.dev.bin_prefetch = b == 3 ? 1 : (b == 4 ? 2 : 0);
+    ih.dev.cplx_tile = c;
   }
 }
 
@@ -386,8 +391,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
                     : (o.flags & FZP_FLAG_BIN_SHALLOW) ? 0
                     : (o.flags & FZP_FLAG_BIN_PREFETCH) ? 3
                     : (o.flags & FZP_FLAG_BIN_DEEP) ? 2 : 4;
+    p.cplx_variant = (o.flags & FZP_FLAG_CPLX_TILE_DUAL) ? 2 : (o.flags & FZP_FLAG_CPLX_TILE_128) ? 1 : 0;
     for (auto &ih : p.inst) ih.dev.seg_len = seg_len;
-    set_variant(p, p.bin_variant);
+    set_variant(p, p.bin_variant + 8 * p.cplx_variant);
     p.lanes_max = o.lanes > 0 && !sa ? o.lanes : 1;  // the padded field is one buffer
     p.lanes = p.lanes_max;
     const int64_t nseg = split ? (N + seg_len - 1) / seg_len : 1;
@@ -1350,20 +1356,32 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
     // so they fit the plan's T buffers), both binary-stripe GEMM tiles, and
     // every lane count
     std::vector<int64_t> segs{seg0};
-    std::vector<int32_t> tiles{p.bin_variant};
+    const int32_t cur = p.bin_variant + 8 * p.cplx_variant;
+    std::vector<int32_t> tiles{cur};
     if (split) {
       for (int64_t sl = 2 * seg0; sl <= 65536 && sl < 2 * p.ap.N; sl *= 2) segs.push_back(sl);
-      bool binary = false;
-      for (const auto &ih : p.inst) binary = binary || ih.dev.n_creases == 0;
-      if (binary) tiles = {0, 1, 2, 3, 4};
+      // binary-stripe variants where a binary mask GEMM runs, complex-stripe
+      // tiles where a complex stripe does
+      bool binary = false, cplx = false;
+      for (const auto &ih : p.inst) {
+        const bool c = ih.dev.n_creases > 0 || (ih.dev.levels != 0 && ih.dev.levels != 2 && ih.dev.levels != 4);
+        cplx = cplx || c;
+        binary = binary || !c;
+      }
+      std::vector<int32_t> bs{p.bin_variant}, cs{p.cplx_variant};
+      if (binary) bs = {0, 1, 2, 3, 4};
+      if (cplx) cs = {0, 1, 2};
+      tiles.clear();
+      for (int32_t c : cs)
+        for (int32_t b : bs) tiles.push_back(b + 8 * c);
     }
     const std::string key = tune_key(p);
     int64_t best_seg = seg0;
-    int32_t best_lanes = p.lanes_max, best_tile = p.bin_variant;
+    int32_t best_lanes = p.lanes_max, best_tile = cur;
     double best_ms = 0.0;
     if (cache_lookup(cache_path, key, best_seg, best_lanes, best_tile) && best_lanes >= 1 &&
         best_lanes <= p.lanes_max && std::find(segs.begin(), segs.end(), best_seg) != segs.end() &&
-        best_tile >= 0 && best_tile <= 4) {
+        best_tile >= 0 && best_tile % 8 <= 4 && best_tile / 8 <= 2) {
       set_decomposition(p, best_seg, best_tile);
       p.lanes = best_lanes;
     } else {

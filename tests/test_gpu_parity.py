@@ -190,6 +190,28 @@ def test_split_creases_ragged(N, M, chunk):
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("N,M,levels", [(2500, 272, 0), (1999, 48, 8), (3000, 128, 0)])
+def test_split_complex_tiles_agree_bit_for_bit(N, M, levels):
+    """The complex-stripe GEMM's 128-column tiles (cplx_tile = 1, and 2 with two
+    work-groups per compute unit) give the 256-column tile's ROI bit for bit (every output sums the same K sequence in
+    the same order) and both agree with the oracle; column tiles past 2M,
+    ragged rows, a creased amplitude plate and a creased 8-level phase plate."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N, levels=levels)
+    cr = crease_draws(31 + N, 2e-3, LAM0, 6) * np.array([1, 1, 0.3, 1])
+    inst = dict(lam=650e-9, M=M, x0=0.5e-6, creases=cr)
+    announce(f"complex tiles N={N} M={M} levels={levels}")
+    _, _, _, (U0,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, chunk_rows=640)
+    _, _, _, (U1,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, chunk_rows=640, cplx_tile=1)
+    _, _, _, (U2,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, chunk_rows=640, cplx_tile=2)
+    assert np.array_equal(U0, U1) and np.array_equal(U0, U2)
+    a = O.Aperture(D=ap["D"], f0=ap["f0"], lambda0=ap["lambda0"], N=N, levels=levels)
+    _, i = oracle_case(ap, inst)
+    ref = O.propagate(a, i, method="bluestein", stripe=512)
+    e = rel_l2(U1, ref)
+    announce(f"  complex rel-L2 {e:.3e}")
+    assert e <= 1e-4
+
+
 @pytest.mark.parametrize("M,creased", [(272, False), (512, True)])
 def test_split_ranges_at_odd_rows_add_up(M, creased):
     """Row ranges that start and end inside the 16- and 32-row blocks of the
