@@ -294,7 +294,10 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
           v[k] = sa_aperture(a, o, u0 + sl + (int64_t)n1 * t);
         } else {
           v[k] = U[base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride];
-          if (PASS == kXAinv) w[k] = a.twNp[(u0 + sl) * t];
+          // W_Np^((u0 + s) t), (u0 + s) t < n1 n2 = Np: evaluated here exactly
+          // as the table entry would be (each element needs a different one,
+          // so a table read is a scattered cache-line fetch per element)
+          if (PASS == kXAinv) w[k] = cexp_turns(-(double)((u0 + sl) * (int64_t)t) / (double)Np);
           if (PASS == kYA && DIR > 0) w[k] = a.twNp[o * t];
         }
       }
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
       slot_of(e, sl, t);
       w[k] = make_double2(1.0, 0.0);
       if (e < total && sl < nslot) {
-        if (PASS == kXAgen) w[k] = a.twNp[(u0 + sl) * t];
+        if (PASS == kXAgen) w[k] = cexp_turns(-(double)((u0 + sl) * (int64_t)t) / (double)Np);
         if (PASS == kYA && DIR < 0) w[k] = a.twNp[o * t];
       }
     }
