@@ -184,6 +184,21 @@ __device__ __forceinline__ double2 sa_aperture(const SaDev &a, int64_t y, int64_
   return cexp_turns(turns);
 }
 
+// The padded field is streamed: each pass reads and writes every element once,
+// so its loads and stores bypass cache allocation (non-temporal), leaving the
+// caches to the twiddle tables.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 field_load(const double2 *p) {
+  const dvec2 v = __builtin_nontemporal_load((const dvec2 *)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void field_store(double2 *p, double2 v) {
+  dvec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, (dvec2 *)p);
+}
+
 // Signed frequency index of k in [0, Np) (numpy's fftfreq order).
 __device__ __forceinline__ double signed_freq(int64_t k, int64_t Np) {
   return (double)(k < (Np + 1) / 2 ? k : k - Np);
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
       int sl, t;
       const int e = threadIdx.x + k * kSaThreads;
       slot_of(e, sl, t);
-      if (e < total && sl < nslot) U[base + sl + t * tstride] = make_double2(0.0, 0.0);
+      if (e < total && sl < nslot) field_store(U + base + sl + t * tstride, make_double2(0.0, 0.0));
     }
     return;
   }
@@ -293,7 +308,7 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
         if (PASS == kXAgen) {
           v[k] = sa_aperture(a, o, u0 + sl + (int64_t)n1 * t);
         } else {
-          v[k] = U[base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride];
+          v[k] = field_load(U + base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride);
           // W_Np^((u0 + s) t), (u0 + s) t < n1 n2 = Np: evaluated here exactly
           // as the table entry would be (each element needs a different one,
           // so a table read is a scattered cache-line fetch per element)
@@ -353,7 +368,7 @@ __global__ __launch_bounds__(kSaThreads, 2) void k_sa_pass(SaDev a, double2 *__r
       if (e >= total || sl >= nslot) continue;
       double2 v = res[t * ld + sl];
       if (PASS == kXAgen || (PASS == kYA && DIR < 0)) v = cmul(v, w[k]);
-      U[base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride] = v;
+      field_store(U + base + (PASS == kXB ? (int64_t)sl * n : (int64_t)sl) + t * tstride, v);
     }
   }
 }
