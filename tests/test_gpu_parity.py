@@ -190,6 +190,19 @@ def test_split_creases_ragged(N, M, chunk):
     assert e <= 1e-4
 
 
+@pytest.mark.parametrize("N,M", [(2500, 272), (1999, 48), (5000, 512)])
+def test_split_binary_variants_agree_bit_for_bit(N, M):
+    """Every binary-stripe GEMM variant sums each output over the same K
+    sequence in the same order: the same ROI bit for bit as the default."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N)
+    inst = dict(lam=600e-9, M=M, y0=0.7e-6)
+    announce(f"binary variants N={N} M={M}")
+    _, _, _, (U4,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, variant=4)
+    for v in (0, 1, 2, 3):
+        _, _, _, (Uv,) = run_gpu(ap, [inst], path="split", allow_undersampled=True, variant=v)
+        assert np.array_equal(Uv, U4), v
+
+
 @pytest.mark.parametrize("N,M,levels", [(2500, 272, 0), (1999, 48, 8), (3000, 128, 0)])
 def test_split_complex_tiles_agree_bit_for_bit(N, M, levels):
     """The complex-stripe GEMM's 128-column tiles (cplx_tile = 1, and 2 with two
