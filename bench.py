@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-sa", action="store_true",
                     help="skip the non-paraxial path on the accuracy study's plate at N = 28672")
     ap.add_argument("--sa-steps", type=int, default=3)
-    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas"], default=None,
+    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate"], default=None,
                     help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
@@ -473,6 +473,19 @@ def run_convergence(dev):
             "reference": {k: round(v, 9) for k, v in ref.items()}, "rows": rows}
 
 
+def run_surrogate(args):
+    """The learned surrogate: CZT data, prior, training, gate, test report; the
+    configured size (20k solves, 300 epochs) with --surrogate, else reduced."""
+    from paper_2609_01978_amd import surrogate as SG
+    from fzp_inputs import workload
+    sw = workload("surrogate")
+    if args.surrogate:
+        return SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
+    r = SG.run(sw, 12000, 2000, 1000, 150, log=log)
+    r["reduced"] = "12000 training, 2000 validation, 1000 test solves, 150 epochs"
+    return r
+
+
 def run_blas(dev):
     """The vendor BF16 GEMM (torch.matmul, hipBLASLt on ROCm) on this GPU, for
     what a library GEMM attains against the same 2.5 PFLOP/s dense peak: a
@@ -533,7 +546,7 @@ def main():
         torch.cuda.set_device(dev)
         run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
                "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev),
-               "blas": lambda: run_blas(dev)}[args.only]
+               "blas": lambda: run_blas(dev), "surrogate": lambda: run_surrogate(args)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -673,13 +686,7 @@ def main():
     if args.convergence:
         out["convergence"] = run_convergence(dev)
     if args.surrogate or not args.no_surrogate:
-        from paper_2609_01978_amd import surrogate as SG
-        sw = workload("surrogate")
-        if args.surrogate:
-            out["surrogate"] = SG.run(sw, sw["n_train"] - 2000, 2000, sw["n_test"], args.surrogate_epochs, log=log)
-        else:
-            out["surrogate"] = SG.run(sw, 12000, 2000, 1000, 150, log=log)
-            out["surrogate"]["reduced"] = "12000 training, 2000 validation, 1000 test solves, 150 epochs"
+        out["surrogate"] = run_surrogate(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
