@@ -419,6 +419,10 @@ __global__ __launch_bounds__(kRedThreads) void k_mtf(const double2 *__restrict__
   }
 }
 
+__global__ void k_mtf_undefined(double *res) {
+  if (threadIdx.x == 0) res[4] = NAN;
+}
+
 __global__ void k_finish(InstDev d, const double *res, double disc_samples, double R2_over_lz2,
                          fzp_metrics_t *out) {
   if (threadIdx.x != 0) return;
@@ -466,11 +470,7 @@ hipError_t launch_metrics(const InstDev &d, const double2 *roi, double disc_samp
     hipLaunchKernelGGL(k_fft2_pass, dim3(grid), dim3(256), 0, st, (const double *)I, F, M, log2M, 1);
     hipLaunchKernelGGL(k_mtf, dim3(1), dim3(kRedThreads), 0, st, (const double2 *)F, M, d.t_mtf, res);
   } else {
-    const double nan = NAN;
-    hipError_t e = hipMemcpyAsync(res + 4, &nan, sizeof(double), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mtf_undefined, dim3(1), dim3(64), 0, st, res);  // the MTF needs a power-of-two M
   }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, d, (const double *)res, disc_samples, d.R2_over_lz2,
                      dev_out);

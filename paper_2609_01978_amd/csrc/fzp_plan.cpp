@@ -530,7 +530,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       off += p.C_bytes;
     }
     p.off_scratch = off;
-    p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + 256;
+    // metric kernels' scratch, then one result record per instance (so that a
+    // batch's metrics come back in one copy)
+    p.scratch_bytes = fzp::metrics_scratch_bytes(p.Mmax) + align256(p.inst.size() * sizeof(fzp_metrics_t));
     off += p.scratch_bytes;
     p.ws_bytes = off;
     if (o.workspace_limit > 0 && p.ws_bytes > o.workspace_limit) {
@@ -1158,17 +1160,19 @@ extern "C" fzp_status_t fzp_metrics(fzp_plan_t h, void *workspace, const double 
   hipStream_t st = (hipStream_t)stream;
   char *ws = (char *)workspace;
   char *scratch = ws + p.off_scratch;
-  fzp_metrics_t *dev_out = (fzp_metrics_t *)(scratch + p.scratch_bytes - 256);
+  // the instances' kernels run one after another on `st` (they share the
+  // scratch); each writes its own result record, copied back in one transfer
+  fzp_metrics_t *dev_out = (fzp_metrics_t *)(scratch + fzp::metrics_scratch_bytes(p.Mmax));
   for (size_t k = 0; k < p.inst.size(); ++k) {
     const InstHost &ih = p.inst[k];
-    hipError_t e = fzp::launch_metrics(ih.dev, (const double2 *)roi_dev + ih.roi_off, (double)p.disc_samples,
-                                       scratch, dev_out, st);
+    const hipError_t e = fzp::launch_metrics(ih.dev, (const double2 *)roi_dev + ih.roi_off,
+                                             (double)p.disc_samples, scratch, dev_out + k, st);
     if (e != hipSuccess) return hip_fail("fzp_metrics: kernels", e);
-    e = hipMemcpyAsync(&out_host[k], dev_out, sizeof(fzp_metrics_t), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return hip_fail("fzp_metrics: copy", e);
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail("fzp_metrics: synchronize", e);
   }
+  hipError_t e = hipMemcpyAsync(out_host, dev_out, p.inst.size() * sizeof(fzp_metrics_t), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail("fzp_metrics: copy", e);
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail("fzp_metrics: synchronize", e);
   return FZP_OK;
 }
 
