@@ -133,7 +133,7 @@ def bluestein_blocks(N: int, B: int) -> int:
 
 def host_cpu():
     """(CPU model, threads this process may use): the affinity mask, capped by
-    OMP_NUM_THREADS when the host sets it (the box's share of its cores)."""
+    OMP_NUM_THREADS when the host sets it (the host's share of its cores)."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
