@@ -94,22 +94,44 @@ __device__ __forceinline__ void dft8(double2 v[8]) {
   v[7] = csub(e3, o3);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft_r(double2 v[8], int R) {
-  switch (R) {
-    case 2: dft2<DIR>(v[0], v[1]); break;
-    case 3: dft3<DIR>(v[0], v[1], v[2]); break;
-    case 4: dft4<DIR>(v[0], v[1], v[2], v[3]); break;
-    case 5: dft5<DIR>(v); break;
-    default: dft8<DIR>(v); break;
-  }
-}
-
 struct Radices {
   int n, nst;
   int r[kSaMaxStages];
   const double2 *tw;  // W_n^k = e^{-2 pi i k / n}, k < n (in LDS)
 };
+
+// One radix-R Stockham stage over G transforms of length n held in LDS at
+// src[t * ld + s] (slot s fastest), into dst; Ns = product of the earlier
+// stages' radices.  R is a compile-time constant, so a butterfly moves exactly
+// R values.
+template <int DIR, int R>
+__device__ __forceinline__ void fft_stage(const double2 *src, double2 *dst, int G, int ld, int n, int Ns,
+                                          const double2 *tw) {
+  const int nb = n / R;           // butterflies per transform
+  const int step = n / (Ns * R);  // W_{Ns R}^m = W_n^(m step)
+  for (int b = threadIdx.x; b < G * nb; b += kSaThreads) {
+    const int s = b % G, j = b / G;
+    const int jm = j % Ns;
+    double2 v[8];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * ld + s];
+    if (jm != 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const double2 w = tw[r * jm * step];
+        v[r] = cmul(v[r], DIR < 0 ? w : conj(w));
+      }
+    }
+    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    if constexpr (R == 3) dft3<DIR>(v[0], v[1], v[2]);
+    if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+    if constexpr (R == 5) dft5<DIR>(v);
+    if constexpr (R == 8) dft8<DIR>(v);
+    const int base = (j - jm) * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * ld + s] = v[r];
+  }
+}
 
 // G transforms of length n held in LDS at src[t * ld + s] (slot s fastest):
 // mixed-radix Stockham stages (autosort, ping-pong between src and dst).
@@ -121,28 +143,12 @@ __device__ double2 *lds_fft(double2 *src, double2 *dst, int G, int ld, const Rad
   const int n = f.n;
   for (int st = 0; st < f.nst; ++st) {
     const int R = f.r[st];
-    const int nb = n / R;           // butterflies per transform
-    const int step = n / (Ns * R);  // W_{Ns R}^m = W_n^(m step)
-    for (int b = threadIdx.x; b < G * nb; b += kSaThreads) {
-      const int s = b % G, j = b / G;
-      const int jm = j % Ns;
-      double2 v[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < R) v[r] = src[(j + r * nb) * ld + s];
-      if (jm != 0) {
-#pragma unroll
-        for (int r = 1; r < 8; ++r)
-          if (r < R) {
-            const double2 w = f.tw[r * jm * step];
-            v[r] = cmul(v[r], DIR < 0 ? w : conj(w));
-          }
-      }
-      dft_r<DIR>(v, R);
-      const int base = (j - jm) * R + jm;
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < R) dst[(base + r * Ns) * ld + s] = v[r];
+    switch (R) {
+      case 2: fft_stage<DIR, 2>(src, dst, G, ld, n, Ns, f.tw); break;
+      case 3: fft_stage<DIR, 3>(src, dst, G, ld, n, Ns, f.tw); break;
+      case 4: fft_stage<DIR, 4>(src, dst, G, ld, n, Ns, f.tw); break;
+      case 5: fft_stage<DIR, 5>(src, dst, G, ld, n, Ns, f.tw); break;
+      default: fft_stage<DIR, 8>(src, dst, G, ld, n, Ns, f.tw); break;
     }
     __syncthreads();
     double2 *t = src;
