@@ -43,6 +43,7 @@ FLAG_BIN_DEEP = 32
 FLAG_CPLX_TILE_128 = 128
 FLAG_CPLX_TILE_DUAL = 256
 FLAG_PARAXIAL_RADII = 64
+FLAG_SPLIT_INT8 = 1024
 STATIC_SCRATCH_BYTES = 64 << 20   # FZP_STATIC_SCRATCH_BYTES
 
 EXPORTED = [
@@ -225,7 +226,7 @@ class Plan:
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
                  chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
                  lanes: int = 0, variant: int = 4, overlap_operand: bool = False, pad: float = 0.0,
-                 paraxial_radii: bool = False, cplx_tile: int = 0):
+                 paraxial_radii: bool = False, cplx_tile: int = 0, int8: bool = False):
         lib = load_library()
         self._lib = lib
         ap = Aperture(D=aperture["D"], f0=aperture["f0"], lambda0=aperture["lambda0"],
@@ -253,6 +254,7 @@ class Plan:
                          3: FLAG_BIN_PREFETCH, 4: 0}[variant]
                       | (FLAG_OVERLAP_OPERAND if overlap_operand else 0)
                       | (FLAG_PARAXIAL_RADII if paraxial_radii else 0)
+                      | (FLAG_SPLIT_INT8 if int8 else 0)
                       | {0: 0, 1: FLAG_CPLX_TILE_128, 2: FLAG_CPLX_TILE_DUAL}[cplx_tile], lanes=int(lanes),
                       pad=float(pad))
         h = ctypes.c_void_p()

@@ -479,7 +479,15 @@ __global__ __launch_bounds__(256) void k_build_col_table(InstDev d, int64_t rows
 // With S and T2 (a 4-level plate) T holds the odd zones' T_u and T2 the
 // second mask's T_v, and the operand is T_disc - (1 - i) T_u - (1 + i) T_v:
 //   re: D_re - (U_re + U_im) - (V_re - V_im),  im: D_im - (U_im - U_re) - (V_im + V_re).
-__device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
+// I8: the planes hold int32 sums of the int8 row pass (raw bits), added
+// exactly in int64 and scaled by 1 / kI8Scale.
+template <bool I8> __device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
+  if (I8) {
+    const int32_t *s32 = (const int32_t *)src;
+    int64_t a = 0;
+    for (int sgi = 0; sgi < nseg; ++sgi) a += s32[(int64_t)sgi * seg_stride_f];
+    return (double)a * (1.0 / kI8Scale);
+  }
   double v = 0.0;
   int sgi = 0;
   for (; sgi + 4 <= nseg; sgi += 4) {
@@ -494,6 +502,7 @@ __device__ __forceinline__ double sum_segments(const float *src, int nseg, int64
   return v;
 }
 
+template <bool I8>
 __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, int64_t row_end,
                                                      const float *__restrict__ T, int nseg, int64_t seg_stride_f,
                                                      int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb,
@@ -505,12 +514,12 @@ __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, 
   const int64_t j = kB0 + kk;
   uint16_t h = 0, l = 0;
   if (j >= row_begin && j < row_end) {
-    double v = sum_segments(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+    double v = sum_segments<I8>(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
     if (T2) {
       // c and its partner column c ^ 1 (re / im of the same ROI column)
-      const double u_o = sum_segments(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
-      const double v_s = sum_segments(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-      const double v_o = sum_segments(T2 + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      const double u_o = sum_segments<I8>(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_s = sum_segments<I8>(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_o = sum_segments<I8>(T2 + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
       // re (c even): U_re + U_im + V_re - V_im; im (c odd): U_im - U_re + V_im + V_re
       v = (c & 1) ? (v - u_o) + (v_s + v_o) : (v + u_o) + (v_s - v_o);
     }
@@ -791,7 +800,8 @@ hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t ro
   const ColSchedule c = col_schedule(M, row_begin, row_end);
   // T -> BF16 hi/lo operand (the row-pass partial planes: column stride = chunk rows)
   const int64_t rs = seg_stride / M;
-  hipLaunchKernelGGL(k_col_operand, dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
+  hipLaunchKernelGGL(d.i8 ? k_col_operand<true> : k_col_operand<false>, dim3((unsigned)(c.KB / 32),
+                     (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
                      row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
                      two_level_fast(d) || four_level_fast(d) ? d.S : nullptr, d.N, d.kmax,
                      four_level_fast(d) ? (const float *)T2 : nullptr);

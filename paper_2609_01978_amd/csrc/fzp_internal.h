@@ -17,6 +17,10 @@ constexpr int kFftLen = 4096;     // Bluestein block FFT length (LDS resident)
 constexpr int kFftThreads = 256;  // threads per FFT work-group
 constexpr int kMaxCreases = 64;
 constexpr int kMaxM = 2048;
+// int8 split table: the kernel row in units of 1 / 16256, 16256 = 127 * 128 the
+// largest scale whose two balanced int8 digits (v = 128 v0 + v1, v1 in
+// [-64, 63]) keep v0 in [-127, 127]
+constexpr double kI8Scale = 16256.0;
 
 // Per-crease constants, precomputed on the host in float64:
 // h_k(x,y) = H_k exp(-(x cos + y sin - rho)^2 * inv2s2)
@@ -63,6 +67,8 @@ struct InstDev {
   int32_t bin_prefetch;    // 8-stage variant: 1 next-stage operands one stage early, 2 interleaved expansion
   int32_t cplx_tile;       // split path, complex stripes: 0 the 256-column GEMM tile, 1 the 128-column tile,
                            // 2 the 128-column tile with a 2-stage ring, two work-groups per CU
+  int32_t i8;              // split path, binary stripes on the int8 matrix cores (FZP_FLAG_SPLIT_INT8):
+                           // table A as two int8 digit planes [2][Npad/64][2M][64]
   int32_t levels;          // 0: binary amplitude plate; L >= 2: L-level phase plate
   double kappa_l;          // phase plates: kappa * (L / 2); level = floor(K kappa_l) mod L
 };

@@ -374,6 +374,15 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         cplx = cplx || ih.in.n_creases > 0 || (ap->levels != 0 && ap->levels != 2 && ap->levels != 4);
         if (ap->levels == 4 && ih.in.n_creases == 0) p.mask_sets = 2;
       }
+    if (o.flags & FZP_FLAG_SPLIT_INT8) {
+      if (!split || cplx) {
+        delete h;
+        return fail(FZP_E_UNSUPPORTED,
+                    "fzp_plan: FZP_FLAG_SPLIT_INT8 needs the split path and crease-free amplitude, 2- or 4-level "
+                    "plates");
+      }
+      for (auto &ih : p.inst) ih.dev.i8 = 1;
+    }
     if (split)
       for (const auto &ih : p.inst)
         if (ih.in.M % 16 != 0) {
@@ -1057,7 +1066,7 @@ uint64_t plan_fingerprint(const Plan &p) {
   Fnv f;
   f.put(p.ap.D), f.put(p.ap.f0), f.put(p.ap.lambda0), f.put(p.ap.pitch), f.put(p.ap.N);
   f.put(p.ap.centre_open), f.put(p.ap.levels), f.put(p.opt.path), f.put(p.chunk_rows), f.put(p.seg_len);
-  f.put(p.bin_variant), f.put(p.roi_elems);
+  f.put(p.bin_variant), f.put(p.roi_elems), f.put(p.inst[0].dev.i8);
   for (const auto &ih : p.inst) {
     f.put(ih.in.lambda), f.put(ih.in.z), f.put(ih.in.x0), f.put(ih.in.y0), f.put(ih.in.half_width);
     f.put(ih.in.M), f.put(ih.in.n_creases);
@@ -1373,7 +1382,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
         binary = binary || !c;
       }
       std::vector<int32_t> bs{p.bin_variant}, cs{p.cplx_variant};
-      if (binary) bs = {0, 1, 2, 3, 4};
+      if (binary && !p.inst[0].dev.i8) bs = {0, 1, 2, 3, 4};  // the int8 row pass has one form
       if (cplx) cs = {0, 1, 2};
       tiles.clear();
       for (int32_t c : cs)
