@@ -64,7 +64,10 @@ def parse():
     ap.add_argument("--no-sa", action="store_true",
                     help="skip the non-paraxial path on the accuracy study's plate at N = 28672")
     ap.add_argument("--sa-steps", type=int, default=3)
-    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate"], default=None,
+    ap.add_argument("--no-int8", action="store_true",
+                    help="skip the int8 row pass (FZP_FLAG_SPLIT_INT8) on the same workload")
+    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate", "int8"],
+                    default=None,
                     help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
@@ -82,6 +85,7 @@ GEMM_SOURCES = ["paper_2609_01978_amd/csrc/fzp_gemm.hip", "paper_2609_01978_amd/
 # MI355X published peaks
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_INT8_TOPS = 5000.0        # dense int8 MFMA
 PEAK_HBM_GBS = 8000.0
 
 
@@ -541,7 +545,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
         return
 
-    if args.only is not None:
+    if args.only is not None and args.only != "int8":
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
@@ -558,8 +562,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    def run_path(path, steps, warmup):
-        plan = P.Plan(ap, [inst], path=path, stripe_rows=S)
+    def run_path(path, steps, warmup, int8=False):
+        plan = P.Plan(ap, [inst], path=path, stripe_rows=S, int8=int8)
         ws, roi = plan.alloc(dev)
         t0 = time.perf_counter()
         plan.prepare(ws)
@@ -587,6 +591,36 @@ def main():
         del ws, roi
         torch.cuda.empty_cache()
         return dict(ms=dt / steps * 1e3, prep_s=t_prep, prof=prof, metrics=metrics, I=I, info=info)
+
+    def int8_section(ref_I, split_I, split_ms):
+        """The int8 row pass on the same workload: samples/s, the row GEMM
+        against the int8 matrix-core peak (8 M int8 operations per disc sample:
+        2 digits x 2 real columns x 2 per multiply-add), intensity against the
+        FP64 path's and the BF16 split's."""
+        r = run_path("split", args.steps, args.warmup, int8=True)
+        pr8 = r["prof"]
+        row8 = pr8["row_ms"] / max(args.steps, 1)
+        ops = 8.0 * M * float(r["info"]["disc_samples"])
+        ach8 = ops / (row8 * 1e-3) / 1e12
+        res = {"gsamples_s": round(samples / (r["ms"] * 1e-3) / 1e9, 3), "ms_per_step": round(r["ms"], 3),
+               "row_pass_ms": round(row8, 3), "mask_bits_ms": round(pr8["mask_ms"] / max(args.steps, 1), 3),
+               "col_pass_ms": round(pr8["col_ms"] / max(args.steps, 1), 3), "metrics": r["metrics"],
+               "roofline": dict(bound="mfma", achieved=round(ach8, 1), peak=PEAK_INT8_TOPS, unit="TOP/s",
+                                frac=round(ach8 / PEAK_INT8_TOPS, 4), kernel="k_row_pass_i8",
+                                launch_ms=round(pr8["row_ms"] / max(pr8["row_launches"], 1), 3),
+                                work="8 M int8 operations per aperture sample inside the disc (two digits)")}
+        if ref_I is not None:
+            e = float(np.linalg.norm(r["I"] - ref_I) / np.linalg.norm(ref_I))
+            res["rel_l2_vs_fp64"] = e
+            res["valid_rel_l2_le_1e-4"] = e <= 1e-4
+        if split_I is not None:
+            res["rel_l2_vs_split_bf16"] = float(np.linalg.norm(r["I"] - split_I) / np.linalg.norm(split_I))
+            res["speedup_vs_split_bf16"] = round(split_ms / r["ms"], 3)
+        return res
+
+    if args.only == "int8":
+        print(json.dumps({"int8": int8_section(None, None, None)}), flush=True)
+        return
 
     log(f"workload {args.workload}: N={N} M={M} stripe={S}")
     split = run_path("split", args.steps, args.warmup)
@@ -674,6 +708,8 @@ def main():
                                                   unit="TFLOP/s", frac=round(ach64 / PEAK_FP64_TFLOPS, 4),
                                                   kernel="k_row_pass_fp64")}
         out["speedup_split_vs_fp64"] = round(fp64["ms"] / split["ms"], 3)
+    if not args.no_int8:
+        out["split_int8"] = int8_section(fp64["I"] if fp64 is not None else None, split["I"], split["ms"])
     if not args.no_batch:
         out["batch64"] = run_batch(args, dev)
     if not args.no_multilevel:

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfzp.so")
 
-SOURCES = ["fzp_plan.cpp", "fzp_fft.hip", "fzp_gemm.hip", "fzp_cplx.hip", "fzp_metrics.hip", "fzp_mlp.hip",
+SOURCES = ["fzp_plan.cpp", "fzp_fft.hip", "fzp_gemm.hip", "fzp_i8.hip", "fzp_cplx.hip", "fzp_metrics.hip", "fzp_mlp.hip",
            "fzp_static.hip", "fzp_sa.hip", "fzp_prior.hip"]
 
 HIPCC_FLAGS = [

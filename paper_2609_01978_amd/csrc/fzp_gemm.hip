@@ -43,32 +43,10 @@ __global__ __launch_bounds__(256) void k_build_split_table(InstDev d, uint16_t *
     const double lin = d.alpha * c * dq;
     const double t = (ph - rint(ph)) - (lin - rint(lin));
     const double2 a = cexp_turns(t);
-    if (d.i8) {
-      // fixed point in units of 1 / kI8Scale, two balanced int8 digits
-      // v = 128 v0 + v1, v1 in [-64, 63], v0 in [-127, 127]; 64-column
-      // blocks, digit planes of 2 M Npad bytes
-      int8_t *A8 = (int8_t *)At;
-      const int64_t b8 = (i >> 6) * (int64_t)(2 * M) * 64 + (i & 63);
-      const int vr = (int)rint(a.x * kI8Scale), vi = (int)rint(a.y * kI8Scale);
-      const int r1 = ((vr + 64) & 127) - 64, i1 = ((vi + 64) & 127) - 64;
-      A8[b8 + (int64_t)(2 * q) * 64] = (int8_t)((vr - r1) >> 7);
-      A8[b8 + (int64_t)(2 * q + 1) * 64] = (int8_t)((vi - i1) >> 7);
-      A8[plane + b8 + (int64_t)(2 * q) * 64] = (int8_t)r1;
-      A8[plane + b8 + (int64_t)(2 * q + 1) * 64] = (int8_t)i1;
-      return;
-    }
     hr = bf16_rne((float)a.x);
     hi_ = bf16_rne((float)a.y);
     lr = bf16_rne((float)(a.x - bf16_to_double(hr)));
     li = bf16_rne((float)(a.y - bf16_to_double(hi_)));
-  } else if (d.i8) {
-    int8_t *A8 = (int8_t *)At;
-    const int64_t b8 = (i >> 6) * (int64_t)(2 * M) * 64 + (i & 63);
-    A8[b8 + (int64_t)(2 * q) * 64] = 0;
-    A8[b8 + (int64_t)(2 * q + 1) * 64] = 0;
-    A8[plane + b8 + (int64_t)(2 * q) * 64] = 0;
-    A8[plane + b8 + (int64_t)(2 * q + 1) * 64] = 0;
-    return;
   }
   const int64_t blk = (i >> 5) * (int64_t)(2 * M) * 32 + (i & 31);
   At[blk + (int64_t)(2 * q) * 32] = hr;
@@ -443,177 +421,6 @@ __global__ __launch_bounds__(BinTile<WR>::threads, BinTile<WR>::per_cu) void k_r
                  r0 + wr * 128 + 4 * lhi, row_begin, row_end);
 }
 
-// ---------------------------------------------------------------------------
-// Row pass on the int8 matrix cores (binary stripes, FZP_FLAG_SPLIT_INT8).
-// The kernel row A_x is held in fixed point, A = v / 16256 with
-// v = 128 v0 + v1 two balanced int8 digits, and the mask is 0 / 1 in int8, so
-//   T = (128 (mask . v0) + mask . v1) / 16256
-// where each product sums exactly in int32 (|sum| <= 65536 (127 * 128 + 64)
-// < 2^31 for K segments up to 65536 columns): the only error is the table's
-// quantisation (at most 3.1e-5 per component), against the BF16 pair's
-// rounding (about 4e-6) in the split form.  One
-// v_mfma_i32_32x32x32_i8 covers 32 columns of K, at twice the BF16 rate.
-//
-// Same work-group tile, wave layout, XCD-aware order, K trimming and direct
-// global -> LDS ring as the binary kernel; a stage is 64 columns of K (two
-// MFMA K-steps: a 64-byte table row per ROI column, two mask words per row).
-// The two digit planes are swept one after the other over the K segment (the
-// accumulators of both would not fit): digit 0, the accumulators times 128,
-// then digit 1.  Partial sums are stored as int32 bits in the float32 partial
-// planes; the column pass converts them (k_col_operand).
-// ---------------------------------------------------------------------------
-constexpr int kKT8 = 64;                         // K columns per stage
-constexpr int kRing8 = 8, kAhead8 = 7;
-constexpr int kSlab8 = kTC * 64;                 // 8 KiB: 128 columns x 64 bytes
-constexpr int kWords8 = 512 * 2 * 4;             // two mask words per tile row
-constexpr int kStage8 = kSlab8 + kWords8;
-constexpr int kLds8 = kRing8 * kStage8;          // 98304
-// each wave copies one slab piece and two word pieces per stage; at a stage's
-// end the copies of the kRing8 - 2 stages after the next may stay in flight
-constexpr int kWait8 = (kRing8 - 2) * 3;
-
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
-
-// 16 mask bits (column order) -> 16 int8 values 0 / 1: each nibble times
-// 0x00204081 puts its bits at 0, 8, 16, 24 (no overlaps, no carries).
-__device__ __forceinline__ i32x4 expand16_i8(uint32_t x) {
-  i32x4 v;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) v[j] = (int32_t)((((x >> (4 * j)) & 0xfu) * 0x00204081u) & 0x01010101u);
-  return v;
-}
-
-template <int N> __device__ __forceinline__ void wait_barrier8() {
-  static_assert(N == 18, "add the count");
-  asm volatile("s_waitcnt vmcnt(18) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-__global__ __launch_bounds__(512, 1) void k_row_pass_i8(InstDev d, int64_t row_begin, int64_t row_end, int n_rt,
-                                                        int n_ct, int seg_lo, int n_seg,
-                                                        const uint32_t *__restrict__ bits, int W, int64_t bits_rows,
-                                                        float *__restrict__ T, int64_t seg_stride_f) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int kTR = 512;
-  char *const sbuf = lds;                          // kRing8 x kSlab8
-  char *const wbuf = lds + kRing8 * kSlab8;        // kRing8 x kWords8
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int G = n_rt * n_ct * n_seg;
-  const int slot = blockIdx.x >> 3;
-  const int g = (slot / 32) * 256 + (blockIdx.x & 7) * 32 + (slot % 32);
-  if (g >= G) return;
-  const int rt = g % n_rt;
-  const int ct = (g / n_rt) % n_ct;
-  const int seg = seg_lo + g / (n_rt * n_ct);
-
-  const int M2 = 2 * d.M;
-  const int64_t r0 = row_begin + (int64_t)rt * kTR;
-  int64_t rl = r0 + kTR - 1;
-  if (rl > row_end - 1) rl = row_end - 1;
-  const int c0 = ct * kTC;
-  const int64_t s_lo = (int64_t)seg * d.seg_len;
-  const int64_t s_hi = s_lo + d.seg_len < d.Npad ? s_lo + d.seg_len : d.Npad;
-  int64_t k_lo, k_hi;
-  tile_chord(d, r0, rl, k_lo, k_hi);
-  k_lo = k_lo / kKT8 * kKT8;
-  k_hi = (k_hi + kKT8 - 1) / kKT8 * kKT8;
-  if (k_lo < s_lo) k_lo = s_lo;
-  if (k_hi > s_hi) k_hi = s_hi;
-
-  // ---- copy roles: thread tid copies the two mask words of tile row tid;
-  // wave w copies slab rows (ROI columns) 16 w .. 16 w + 15, lane L chunk L & 3
-  // of row 16 w + L / 4 from global chunk (L & 3) ^ swz(row).  Columns past 2M
-  // read column 0: they feed only accumulators that are never stored.
-  const uint32_t *wsrc = bits + (r0 + tid - row_begin);
-  const int R = wave * 16 + (lane >> 2);
-  const int gc = c0 + R < M2 ? c0 + R : 0;
-  const int64_t plane = (int64_t)M2 * d.Npad;     // bytes per digit plane
-  const int8_t *bsrc0 = (const int8_t *)d.A + (int64_t)gc * 64 + 16 * ((lane & 3) ^ swz(R));
-
-  // ---- compute role: wave (wr, wc) covers rows wr*128.., columns wc*64..
-  const int wr = wave >> 1, wc = wave & 1;
-  const int l32 = lane & 31, lhi = lane >> 5;
-  const int lsw = swz(l32);
-  const int cks0 = ((0 + lhi) ^ lsw) << 4, cks1 = ((2 + lhi) ^ lsw) << 4;
-  const int brow = (wc * 64 + l32) * 64;
-
-  i32x16 acc[4][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
-
-  if (k_lo < k_hi) {
-    const int kb = (int)k_lo;
-    const int nst = (int)((k_hi - k_lo) / kKT8);
-    const int klast = (int)d.Npad - kKT8;
-#pragma unroll 1
-    for (int dg = 0; dg < 2; ++dg) {
-      const int8_t *bsrc = bsrc0 + dg * plane;
-      auto copy_stage = [&](int s) {
-        const int k = min(kb + s * kKT8, klast);
-        __builtin_amdgcn_global_load_lds((const void *)(bsrc + (int64_t)(k >> 6) * M2 * 64),
-                                         (__attribute__((address_space(3))) void *)(sbuf + (s % kRing8) * kSlab8 +
-                                                                                    wave * 1024),
-                                         16, 0, 0);
-        const int wi = k >> 5;  // k <= Npad - 64: words wi and wi + 1 exist
-        char *wd = wbuf + (s % kRing8) * kWords8 + wave * 256;
-        __builtin_amdgcn_global_load_lds((const void *)(wsrc + (int64_t)wi * bits_rows),
-                                         (__attribute__((address_space(3))) void *)wd, 4, 0, 0);
-        __builtin_amdgcn_global_load_lds((const void *)(wsrc + (int64_t)(wi + 1) * bits_rows),
-                                         (__attribute__((address_space(3))) void *)(wd + kTR * 4), 4, 0, 0);
-      };
-      for (int s = 0; s < kAhead8; ++s) copy_stage(s);
-      wait_barrier8<kWait8>();
-      for (int s = 0; s < nst; ++s) {
-        copy_stage(s + kAhead8);
-        const uint32_t *sw = (const uint32_t *)(wbuf + (s % kRing8) * kWords8) + wr * 128 + l32;
-        const char *sb = sbuf + (s % kRing8) * kSlab8 + brow;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          i32x4 bq[2], aq[4];
-#pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
-            bq[cb] = __builtin_bit_cast(i32x4, lds_ld16(sb + cb * 32 * 64 + (ks ? cks1 : cks0)));
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb) aq[rb] = expand16_i8((sw[rb * 32 + ks * kTR] >> (16 * lhi)) & 0xffffu);
-#pragma unroll
-          for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-              acc[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aq[rb], bq[cb], acc[rb][cb], 0, 0, 0);
-        }
-        wait_barrier8<kWait8>();
-      }
-      // drain the copies past the end, and let every wave finish reading the
-      // ring before the next digit's prologue overwrites it
-      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-      if (dg == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[a][b][e] *= 128;
-      }
-    }
-  }
-  // epilogue: the int32 sums as raw bits in the float32 partial planes
-  f32x16 out[4][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[a][b][e] = __int_as_float(acc[a][b][e]);
-  store_partials(out, T + (int64_t)(seg - seg_lo) * seg_stride_f, seg_stride_f / M2, c0 + wc * 64 + l32, M2,
-                 r0 + wr * 128 + 4 * lhi, row_begin, row_end);
-}
-
 }  // namespace
 
 hipError_t init_split_attributes() {
@@ -635,8 +442,6 @@ hipError_t init_split_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_row_pass_split<2, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             BinTile<2, 4>::lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_row_pass_i8, hipFuncAttributeMaxDynamicSharedMemorySize, kLds8);
   if (e == hipSuccess) e = init_cplx_attributes();
   if (e == hipSuccess) done.store(true, std::memory_order_release);
   return e;
@@ -739,17 +544,6 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
   hipError_t e = init_split_attributes();
   if (e != hipSuccess) return e;
   const int n_seg = seg_hi - seg_lo;
-  if (d.i8) {
-    const int64_t rows = row_end - row_begin;
-    const int W = (int)(d.Npad / 32);
-    const int n_rt = (int)((rows + 511) / 512);
-    const int n_ct = (2 * d.M + kTC - 1) / kTC;
-    const int64_t G = (int64_t)n_rt * n_ct * n_seg;
-    const int64_t grid = (G + 255) / 256 * 256;  // whole rounds of 32 work-groups on each of 8 XCDs
-    hipLaunchKernelGGL(k_row_pass_i8, dim3((unsigned)grid), dim3(512), kLds8, st, d, row_begin, row_end, n_rt, n_ct,
-                       seg_lo, n_seg, bits, W, bits_rows_pad(rows), (float *)T, 2 * seg_stride);
-    return hipGetLastError();
-  }
   if (d.bin_tile_rows == 256)
     return launch_bin<2, 4, false, false>(d, row_begin, row_end, T, seg_stride, bits, seg_lo, n_seg, st);
   if (d.bin_ring == 8 && d.bin_prefetch == 1)

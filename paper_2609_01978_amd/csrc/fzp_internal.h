@@ -193,6 +193,14 @@ hipError_t launch_row_pass_split_cplx(const InstDev &d, int64_t row_begin, int64
                                       int64_t seg_stride, const uint16_t *G, hipStream_t st);
 hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin, int64_t row_end,
                                  float2 *T, int64_t seg_stride, const uint32_t *bits, hipStream_t st);
+// Int8 form of the binary row pass (fzp_i8.hip, d.i8): the digit table in the
+// split table's space, then the same partial planes as launch_row_pass_split,
+// holding int32 sums in units of 1 / kI8Scale.
+int64_t bits_rows_pad(int64_t rows);  // mask-bit rows of a chunk, padded to the 512-row tile
+hipError_t launch_build_i8_table(const InstHost &ih, char *ws, hipStream_t st);
+hipError_t init_i8_attributes();  // its LDS attribute (outside graph capture)
+hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
+                              const uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,
                            hipStream_t st);  // FP64 path
 // Split path column pass as a split-BF16 GEMM (fzp_cplx.hip): the column kernel

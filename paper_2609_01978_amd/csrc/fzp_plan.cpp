@@ -703,7 +703,7 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
       e = fzp::launch_build_tables(p, ih, ws, st);
       if (e != hipSuccess) return hip_fail("fzp_prepare: table kernel", e);
       if (p.opt.path == FZP_PATH_SPLIT_BF16 && ih.table_owner == (int32_t)k) {
-        e = fzp::launch_build_split_table(p, ih, ws, st);
+        e = ih.dev.i8 ? fzp::launch_build_i8_table(ih, ws, st) : fzp::launch_build_split_table(p, ih, ws, st);
         if (e != hipSuccess) return hip_fail("fzp_prepare: split table kernel", e);
         if (ih.dev.S) {
           e = fzp::launch_build_prefix_table(ih.dev, (double2 *)(ws + ih.off_S), st);
@@ -717,6 +717,7 @@ extern "C" fzp_status_t fzp_prepare(fzp_plan_t h, void *workspace, void *stream)
     }
     if (p.opt.path == FZP_PATH_SPLIT_BF16) {
       hipError_t e = fzp::init_split_attributes();
+      if (e == hipSuccess && p.inst[0].dev.i8) e = fzp::init_i8_attributes();
       if (e != hipSuccess) return hip_fail("fzp_prepare: kernel attributes", e);
     }
     if (p.opt.path == FZP_PATH_SA_CZT) {
@@ -926,11 +927,13 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
       e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride,
                                           (const uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), st);
     else if (split) {
-      e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride,
-                                     (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set), st);
+      const uint32_t *bits = (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set);
+      const uint32_t *bits2 = (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes);
+      e = ih.dev.i8 ? fzp::launch_row_pass_i8(ih.dev, r0, r1, (float2 *)T, seg_stride, bits, st)
+                    : fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T, seg_stride, bits, st);
       if (e == hipSuccess && four)
-        e = fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T2, seg_stride,
-                                       (const uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes), st);
+        e = ih.dev.i8 ? fzp::launch_row_pass_i8(ih.dev, r0, r1, (float2 *)T2, seg_stride, bits2, st)
+                      : fzp::launch_row_pass_split(ih.dev, p.S, r0, r1, (float2 *)T2, seg_stride, bits2, st);
     }
     else
       e = fzp::launch_row_pass_fp64(ih.dev, r0, r1, (double2 *)T, st);

@@ -44,3 +44,7 @@ def test_json_line_at_the_small_workload():
     assert ro["mfma_busy"] is None
     assert d["valid_rel_l2_le_1e-4"] is True and d["rel_l2_split_vs_fp64"] <= 1e-4
     assert d["fp64_bluestein"]["roofline"]["bound"] == "alu"
+    i8 = d["split_int8"]
+    assert i8["gsamples_s"] > 0 and i8["valid_rel_l2_le_1e-4"] is True
+    assert i8["roofline"]["unit"] == "TOP/s" and i8["roofline"]["peak"] == 5000.0
+    assert 0 < i8["roofline"]["frac"] < 1
