@@ -81,6 +81,7 @@ def log(msg):
 # sources of the dominant kernel (k_row_pass_split); its committed HBM counters
 # are reported only while these are unchanged
 GEMM_SOURCES = ["paper_2609_01978_amd/csrc/fzp_gemm.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
+I8_SOURCES = ["paper_2609_01978_amd/csrc/fzp_i8.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
 
 # MI355X published peaks
 PEAK_BF16_TFLOPS = 2500.0
@@ -607,6 +608,13 @@ def main():
                "col_pass_ms": round(pr8["col_ms"] / max(args.steps, 1), 3), "metrics": r["metrics"],
                "roofline": dict(bound="mfma", achieved=round(ach8, 1), peak=PEAK_INT8_TOPS, unit="TOP/s",
                                 frac=round(ach8 / PEAK_INT8_TOPS, 4), kernel="k_row_pass_i8",
+                                traffic=committed_traffic(I8_SOURCES, "profiles/hbm_traffic_k_row_pass_i8_fzp1m.md")
+                                if args.workload == "fzp1m" else None,
+                                mfma_busy=committed_value(I8_SOURCES, "profiles/sq_counters_k_row_pass_i8_fzp1m.md",
+                                                          "mfma_busy_fraction_of_cycles")
+                                if args.workload == "fzp1m" else None,
+                                committed_from="profiles/hbm_traffic_k_row_pass_i8_fzp1m.md (traffic), "
+                                               "profiles/sq_counters_k_row_pass_i8_fzp1m.md (mfma_busy)",
                                 launch_ms=round(pr8["row_ms"] / max(pr8["row_launches"], 1), 3),
                                 work="8 M int8 operations per aperture sample inside the disc (two digits)")}
         if ref_I is not None:
