@@ -199,6 +199,9 @@ hipError_t launch_row_pass_split(const InstDev &d, int32_t S, int64_t row_begin,
 int64_t bits_rows_pad(int64_t rows);  // mask-bit rows of a chunk, padded to the 512-row tile
 hipError_t launch_build_i8_table(const InstHost &ih, char *ws, hipStream_t st);
 hipError_t init_i8_attributes();  // its LDS attribute (outside graph capture)
+// the chunk's zone-mask bits in the int8 row pass's word order (Npad a multiple of 128)
+hipError_t launch_mask_bits_i8(const InstDev &d, int64_t row_begin, int64_t row_end, uint32_t *bits, hipStream_t st,
+                               uint32_t *bits2 = nullptr);
 hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
                               const uint32_t *bits, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,

@@ -464,7 +464,9 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       ih.off_S = 0;
     }
     if (split) {
-      const int64_t npad = (N + 63) / 64 * 64;
+      // K padded to the GEMM stage: 64 columns, 128 for the int8 row pass
+      const int64_t kal = p.inst[0].dev.i8 ? 128 : 64;
+      const int64_t npad = (N + kal - 1) / kal * kal;
       for (int k = 0; k < n_inst; ++k) {
         InstHost &ih = p.inst[k];
         // instances with the same ROI grid and lambda z share one operand table
@@ -888,10 +890,9 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     if (pe == hipSuccess)
       pe = cplx ? fzp::launch_stripe_cplx(ih.dev, chunks[i].r0, chunks[i].r1,
                                           (uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), ax)
-                : fzp::launch_mask_bits(ih.dev, chunks[i].r0, chunks[i].r1,
-                                        (uint32_t *)(ws + p.off_bits[lane] + b * bits_set), ax,
-                                        four ? (uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes)
-                                             : nullptr);
+                : (ih.dev.i8 ? fzp::launch_mask_bits_i8 : fzp::launch_mask_bits)(
+                      ih.dev, chunks[i].r0, chunks[i].r1, (uint32_t *)(ws + p.off_bits[lane] + b * bits_set), ax,
+                      four ? (uint32_t *)(ws + p.off_bits[lane] + b * bits_set + p.bits_bytes) : nullptr);
     if (pe == hipSuccess) pe = end_mark(2, ax);
     if (pe == hipSuccess && overlap) pe = hipEventRecord(ev[1 + b], ax);
     return pe;

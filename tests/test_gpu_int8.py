@@ -51,7 +51,7 @@ def oracle(ap, inst):
 
 
 @pytest.mark.parametrize("L,N,M", [(0, 3000, 48), (0, 2500, 128), (0, 4096, 384), (0, 777, 16),
-                                   (2, 2048, 128), (4, 3000, 144)])
+                                   (2, 2048, 128), (4, 3000, 144), (4, 2048, 64)])
 def test_int8_full_roi(L, N, M):
     ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=N, levels=L, centre_open=1 if N == 777 else 0)
     inst = dict(lam=600e-9 if L else LAM0, M=M, x0=1e-6 if L else 0.0)
