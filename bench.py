@@ -274,8 +274,11 @@ def run_multilevel(args, dev, levels=None):
     inst = dict(lam=w["lambda0"], M=w["M"])
     samples = float(w["N"]) ** 2
     res, I = {}, {}
-    for path in ("split", "fp64"):
-        plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"] if path == "split" else 0)
+    # the int8 row pass covers the 2- and 4-level plates (binary-mask products)
+    for path in ("split", "fp64") + (("split_int8",) if L in (2, 4) else ()):
+        i8 = path == "split_int8"
+        plan = P.Plan(ap, [inst], path="fp64" if path == "fp64" else "split",
+                      stripe_rows=0 if path == "fp64" else w["stripe"], int8=i8)
         ws, roi = plan.alloc(dev)
         plan.prepare(ws)
         plan.propagate(ws, roi)
@@ -291,7 +294,7 @@ def run_multilevel(args, dev, levels=None):
         I[path] = plan.roi_view(roi, 0).abs().square().cpu().numpy()
         res[path] = {"gsamples_s": round(samples / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
                      "de": m["de"], "fwhm_x": m["fwhm_x"], "strehl": m["strehl"]}
-        if path == "split":
+        if path != "fp64":
             # the row GEMM's own time (HIP events around its launches, one more
             # propagation): 8 M flops per disc sample for a 2-level plate (the
             # binary GEMM of its odd zones), 16 M for a 4-level plate (two binary
@@ -305,9 +308,11 @@ def run_multilevel(args, dev, levels=None):
             per = (8.0 if L == 2 else 16.0 if L == 4 else 24.0) * w["M"]
             flops = per * float(plan.info()["disc_samples"])
             ach = flops / (pr["row_ms"] * 1e-3) / 1e12
-            res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS,
-                                         unit="TFLOP/s", frac=round(ach / PEAK_BF16_TFLOPS, 4),
-                                         kernel="k_row_pass_split" if L in (2, 4) else "k_row_pass_split_cplx",
+            peak = PEAK_INT8_TOPS if i8 else PEAK_BF16_TFLOPS
+            res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=peak,
+                                         unit="TOP/s" if i8 else "TFLOP/s", frac=round(ach / peak, 4),
+                                         kernel="k_row_pass_i8" if i8 else
+                                         "k_row_pass_split" if L in (2, 4) else "k_row_pass_split_cplx",
                                          launch_ms=round(
                                              pr["row_ms"] / max(pr["row_launches"], 1), 3),
                                          work=f"{per / w['M']:.0f} M flops per disc sample")
@@ -316,11 +321,17 @@ def run_multilevel(args, dev, levels=None):
     e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
     x = math.pi / L
     lobe = 1.0 - float(special.j0(special.jn_zeros(1, 1)[0])) ** 2
-    return {"workload": f"{L}-level phase FZP D={w['D']} m f/5 lambda0=632.8 nm, N={w['N']}^2, ROI {w['M']}^2",
-            "steps": args.multilevel_steps, "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
-            "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
-            "de_ladder_sinc2": round((math.sin(x) / x) ** 2 * lobe, 6),
-            "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
+    out = {"workload": f"{L}-level phase FZP D={w['D']} m f/5 lambda0=632.8 nm, N={w['N']}^2, ROI {w['M']}^2",
+           "steps": args.multilevel_steps, "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
+           "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
+           "de_ladder_sinc2": round((math.sin(x) / x) ** 2 * lobe, 6),
+           "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
+    if "split_int8" in res:
+        e8 = float(np.linalg.norm(I["split_int8"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
+        out["split_int8"] = dict(res["split_int8"], **{
+            "rel_l2_vs_fp64": e8, "valid_rel_l2_le_1e-4": e8 <= 1e-4,
+            "speedup_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split_int8"]["ms_per_step"], 3)})
+    return out
 
 
 def run_configs(dev, steps: int = 3):
