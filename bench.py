@@ -189,8 +189,8 @@ def cpu_baseline(w, rows_n: int):
 def run_batch(args, dev):
     """64 instances of the 20 mm element (16 wavelengths x 4 crease maps, ROI
     sizes from {256, 512, 1024}), each path captured as one HIP graph; the split
-    plan is autotuned first.  Valid when every instance's split intensity is
-    within rel-L2 1e-4 of the FP64 path's."""
+    plans (BF16, and the int8 row pass) are autotuned first.  Valid when every
+    instance's split intensity is within rel-L2 1e-4 of the FP64 path's."""
     import numpy as np
     import torch
     import paper_2609_01978_amd as P
@@ -200,11 +200,12 @@ def run_batch(args, dev):
     insts = batch64_instances()
     samples = len(insts) * float(w["N"]) ** 2
     res, I = {}, {}
-    for path in ("split", "fp64"):
-        plan = P.Plan(ap, insts, path=path, lanes=2)
+    for path in ("split", "split_int8", "fp64"):
+        i8 = path == "split_int8"
+        plan = P.Plan(ap, insts, path="fp64" if path == "fp64" else "split", lanes=2, int8=i8)
         ws, roi = plan.alloc(dev)
         plan.prepare(ws)
-        tune = plan.autotune(ws, roi, args.tune_cache) if path == "split" else None
+        tune = plan.autotune(ws, roi, args.tune_cache if not i8 else None) if path != "fp64" else None
         g = plan.graph(ws, roi)
         g.launch()
         torch.cuda.synchronize()
@@ -221,36 +222,44 @@ def run_batch(args, dev):
             res[path]["autotune"] = tune
         del g, ws, roi
         torch.cuda.empty_cache()
+        if path == "fp64":
+            continue
+        # Roofline of the batch's dominant kernel, the complex-stripe row GEMM:
+        # 24 M operations per disc sample of a creased instance (three split
+        # products of a complex product; BF16 pairs, or int8 digits).  One more
+        # propagation on a one-lane plan with HIP events around each launch, so
+        # that no interval holds another lane's kernels.
+        plan = P.Plan(ap, insts, path="split", lanes=1, int8=i8)
+        ws, roi = plan.alloc(dev)
+        plan.propagate(ws, roi)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        plan.profile_read(reset=True)
+        plan.propagate(ws, roi)
+        torch.cuda.synchronize()
+        pr = plan.profile_read(reset=True)
+        disc = float(plan.info()["disc_samples"])
+        flops = sum(24.0 * inst["M"] * disc for inst in insts)
+        ach = flops / (pr["row_ms"] * 1e-3) / 1e12
+        peak = PEAK_INT8_TOPS if i8 else PEAK_BF16_TFLOPS
+        res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=peak,
+                                     unit="TOP/s" if i8 else "TFLOP/s", frac=round(ach / peak, 4),
+                                     kernel="k_row_pass_i8_cplx" if i8 else "k_row_pass_split_cplx",
+                                     launches=pr["row_launches"], row_gemm_ms=round(pr["row_ms"], 3),
+                                     stripe_ms=round(pr["mask_ms"], 3), col_pass_ms=round(pr["col_ms"], 3),
+                                     flops_per_batch=flops,
+                                     work="24 M operations per disc sample of each creased instance (one lane, "
+                                          "default K segments)")
+        del ws, roi, plan
+        torch.cuda.empty_cache()
     errs = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(I["split"], I["fp64"])]
-    # Roofline of the batch's dominant kernel, the complex-stripe row GEMM
-    # (k_row_pass_split_cplx): 24 M flops per disc sample of a creased instance
-    # (three split products of a complex product).  One more propagation on a
-    # one-lane plan with HIP events around each launch, so that no interval
-    # holds another lane's kernels.
-    plan = P.Plan(ap, insts, path="split", lanes=1)
-    ws, roi = plan.alloc(dev)
-    plan.propagate(ws, roi)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read(reset=True)
-    plan.propagate(ws, roi)
-    torch.cuda.synchronize()
-    pr = plan.profile_read(reset=True)
-    disc = float(plan.info()["disc_samples"])
-    flops = sum(24.0 * inst["M"] * disc for inst in insts)
-    ach = flops / (pr["row_ms"] * 1e-3) / 1e12
-    res["split"]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
-                                    frac=round(ach / PEAK_BF16_TFLOPS, 4), kernel="k_row_pass_split_cplx",
-                                    launches=pr["row_launches"], row_gemm_ms=round(pr["row_ms"], 3),
-                                    stripe_ms=round(pr["mask_ms"], 3), col_pass_ms=round(pr["col_ms"], 3),
-                                    flops_per_batch=flops,
-                                    work="24 M flops per disc sample of each creased instance (one lane, "
-                                         "default K segments)")
-    del ws, roi, plan
-    torch.cuda.empty_cache()
+    errs8 = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(I["split_int8"], I["fp64"])]
+    res["split_int8"].update({"max_rel_l2_vs_fp64": max(errs8), "valid_rel_l2_le_1e-4": max(errs8) <= 1e-4,
+                              "speedup_vs_fp64": round(res["fp64"]["ms_per_batch"] /
+                                                       res["split_int8"]["ms_per_batch"], 3)})
     return {"workload": "64 instances: D=20 mm f/5 N=32768^2, lambda 500-800 nm x 4 crease maps (8 creases), "
                         "M in {256,512,1024}", "instances": len(insts), "steps": args.batch_steps,
-            "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
+            "split_bf16": res["split"], "fp64_bluestein": res["fp64"], "split_int8": res["split_int8"],
             "max_rel_l2_split_vs_fp64": max(errs), "valid_rel_l2_le_1e-4": max(errs) <= 1e-4,
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_batch"] / res["split"]["ms_per_batch"], 3)}
 

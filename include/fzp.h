@@ -108,13 +108,14 @@ typedef int32_t fzp_status_t;
 #define FZP_FLAG_PARAXIAL_RADII 64    /* FZP_PATH_SA_CZT: the paraxial radii of Eq. 4 (r_n^2 = n
                                          lambda0 f0) instead of Eq. 3, e.g. to compare with the
                                          Fresnel paths */
-#define FZP_FLAG_SPLIT_INT8 1024      /* split path, crease-free plates (binary amplitude, 2- and
-                                         4-level phase): the row pass on the int8 matrix cores, the
-                                         kernel row in fixed point of step 1/16256 (two int8
-                                         digits, exact int32 sums): half the BF16 pair's matrix-core
-                                         work, quantisation error <= 3.1e-5 per kernel element
-                                         instead of the pair's ~4e-6 rounding; FZP_E_UNSUPPORTED
-                                         with creases, other levels or another path */
+#define FZP_FLAG_SPLIT_INT8 1024      /* split path: the row pass on the int8 matrix cores, the
+                                         kernel row (and a complex stripe: creases, L-level
+                                         plates) in fixed point of step 1/16256, two int8 digits,
+                                         exact int32 sums per K segment: half the BF16 split's
+                                         matrix-core work; quantisation error <= 3.1e-5 per element
+                                         (the BF16 pair rounds to ~4e-6), and for complex stripes
+                                         the digit-1 x digit-1 product (<= 1.5e-5) left out;
+                                         FZP_E_UNSUPPORTED on another path */
 #define FZP_FLAG_OVERLAP_OPERAND 16   /* split path: make each chunk's stripe operand on an internal
                                          auxiliary stream one chunk ahead of its GEMM (two operand
                                          buffers); not under stream capture: fzp_graph_create,

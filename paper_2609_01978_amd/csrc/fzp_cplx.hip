@@ -95,7 +95,11 @@ __device__ __forceinline__ uint16_t bf16_cvt(float f) { return __builtin_bit_cas
 
 // PHASE: an L-level phase plate (levels != 0).  Crease-free 2- and 4-level
 // plates never come here: they are sums of binary masks (k_col_operand).
-template <bool PHASE>
+// I8: the int8 row pass's operand instead of the BF16 pair: the same layout
+// with one byte per sample, planes v = s0_re, s1_re, s0_im, s1_im, the two
+// balanced digits of rint(kI8Scale g) (as the int8 table), and the written
+// blocks rounded to that pass's 32-column stages.
+template <bool PHASE, bool I8 = false>
 __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_begin, int64_t row_end,
                                                      int64_t rows_pad, int64_t kb0, int64_t nkb,
                                                      uint16_t *__restrict__ G) {
@@ -118,8 +122,9 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
     const int64_t r0 = row_begin + (int64_t)blockIdx.x * kCTR;
     const int64_t r1 = r0 + kCTR - 1 < row_end - 1 ? r0 + kCTR - 1 : row_end - 1;
     tile_chord(d, r0, r1, t_lo, t_hi);
-    t_lo = t_lo / 16 * 16;
-    t_hi = (t_hi + 15) / 16 * 16;
+    constexpr int kAl = I8 ? 32 : 16;
+    t_lo = t_lo / kAl * kAl;
+    t_hi = (t_hi + kAl - 1) / kAl * kAl;
   }
   for (int64_t kb = blockIdx.y; kb < nkb; kb += gridDim.y) {
     const int64_t i0 = 16 * (kb0 + kb);
@@ -179,6 +184,26 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
         g *= r;
         r *= q;
       }
+    }
+    if constexpr (I8) {
+      uint32_t w8[4][4] = {};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        float sn, cs;
+        sincos_turns(turns[e], sn, cs);
+        const bool o = (open >> e) & 1u;
+        const int vr = o ? (int)rintf(cs * (float)kI8Scale) : 0, vi = o ? (int)rintf(sn * (float)kI8Scale) : 0;
+        const int lr = ((vr + 64) & 127) - 64, li = ((vi + 64) & 127) - 64;
+        const uint32_t dg[4] = {(uint32_t)(((vr - lr) >> 7) & 0xff), (uint32_t)(lr & 0xff),
+                                (uint32_t)(((vi - li) >> 7) & 0xff), (uint32_t)(li & 0xff)};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w8[v][e >> 2] |= dg[v] << (8 * (e & 3));
+      }
+      int8_t *G8 = (int8_t *)G;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        *(u32x4 *)(G8 + v * plane + (kb * rows_pad + rl) * 16) = u32x4{w8[v][0], w8[v][1], w8[v][2], w8[v][3]};
+      continue;
     }
     uint32_t w[4][8];
 #pragma unroll
@@ -479,15 +504,20 @@ __global__ __launch_bounds__(256) void k_build_col_table(InstDev d, int64_t rows
 // With S and T2 (a 4-level plate) T holds the odd zones' T_u and T2 the
 // second mask's T_v, and the operand is T_disc - (1 - i) T_u - (1 + i) T_v:
 //   re: D_re - (U_re + U_im) - (V_re - V_im),  im: D_im - (U_im - U_re) - (V_im + V_re).
-// I8: the planes hold int32 sums of the int8 row pass (raw bits), added
-// exactly in int64 and scaled by 1 / kI8Scale.
-template <bool I8> __device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
-  if (I8) {
-    const int32_t *s32 = (const int32_t *)src;
-    int64_t a = 0;
-    for (int sgi = 0; sgi < nseg; ++sgi) a += s32[(int64_t)sgi * seg_stride_f];
-    return (double)a * (1.0 / kI8Scale);
-  }
+// The int8 row pass's planes hold int32 sums (raw bits), added exactly in int64.
+__device__ __forceinline__ int64_t sum_segments_i32(const float *src, int nseg, int64_t seg_stride_f) {
+  const int32_t *s32 = (const int32_t *)src;
+  int64_t a = 0;
+  for (int sgi = 0; sgi < nseg; ++sgi) a += s32[(int64_t)sgi * seg_stride_f];
+  return a;
+}
+
+// MODE 0: float32 planes (split-BF16 row pass); 1: int32 sums of the int8
+// binary row pass, in units of 1 / kI8Scale; 2: the int8 complex row pass, T
+// the digit-0 products and T2 the cross products, in units of 1 / kI8Scale^2
+// after weighting 128^2 and 128.
+template <int MODE> __device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
+  if constexpr (MODE == 1) return (double)sum_segments_i32(src, nseg, seg_stride_f) * (1.0 / kI8Scale);
   double v = 0.0;
   int sgi = 0;
   for (; sgi + 4 <= nseg; sgi += 4) {
@@ -502,7 +532,7 @@ template <bool I8> __device__ __forceinline__ double sum_segments(const float *s
   return v;
 }
 
-template <bool I8>
+template <int MODE>
 __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, int64_t row_end,
                                                      const float *__restrict__ T, int nseg, int64_t seg_stride_f,
                                                      int64_t rs, int64_t kB0, int64_t KB, uint16_t *__restrict__ Tb,
@@ -514,12 +544,19 @@ __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, 
   const int64_t j = kB0 + kk;
   uint16_t h = 0, l = 0;
   if (j >= row_begin && j < row_end) {
-    double v = sum_segments<I8>(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-    if (T2) {
+    double v;
+    if constexpr (MODE == 2) {
+      const int64_t hi = sum_segments_i32(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+      const int64_t x = sum_segments_i32(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+      v = (double)(16384 * hi + 128 * x) * (1.0 / (kI8Scale * kI8Scale));
+    } else {
+      v = sum_segments<MODE>(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+    }
+    if (MODE != 2 && T2) {
       // c and its partner column c ^ 1 (re / im of the same ROI column)
-      const double u_o = sum_segments<I8>(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
-      const double v_s = sum_segments<I8>(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-      const double v_o = sum_segments<I8>(T2 + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      const double u_o = sum_segments<MODE>(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_s = sum_segments<MODE>(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+      const double v_o = sum_segments<MODE>(T2 + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
       // re (c even): U_re + U_im + V_re - V_im; im (c odd): U_im - U_re + V_im + V_re
       v = (c & 1) ? (v - u_o) + (v_s + v_o) : (v + u_o) + (v_s - v_o);
     }
@@ -596,8 +633,11 @@ void split_stripe_extent(const InstDev &d, int64_t row_begin, int64_t row_end, i
   int64_t lo, hi;
   split_chunk_chord(d, row_begin, row_end, lo, hi);
   rows_pad = (row_end - row_begin + kCTR - 1) / kCTR * kCTR;
-  kb0 = lo / 16;
-  nkb = hi > lo ? (hi + 15) / 16 - kb0 : 0;
+  // 16-column blocks; an even count from an even block for the int8 row
+  // pass's 32-column stages
+  const int64_t al = d.i8 ? 32 : 16;
+  kb0 = lo / al * al / 16;
+  nkb = hi > lo ? (hi + al - 1) / al * al / 16 - kb0 : 0;
 }
 
 hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, uint16_t *G, hipStream_t st) {
@@ -613,7 +653,13 @@ hipError_t launch_stripe_cplx(const InstDev &d, int64_t row_begin, int64_t row_e
   if (gy > nkb) gy = nkb;
   if (gy > 65535) gy = 65535;
   const dim3 grid((unsigned)gx, (unsigned)gy);
-  if (d.levels != 0)
+  if (d.levels != 0 && d.i8)
+    hipLaunchKernelGGL((k_stripe_cplx<true, true>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
+                       nkb, G);
+  else if (d.i8)
+    hipLaunchKernelGGL((k_stripe_cplx<false, true>), grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0,
+                       nkb, G);
+  else if (d.levels != 0)
     hipLaunchKernelGGL(k_stripe_cplx<true>, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
   else
     hipLaunchKernelGGL(k_stripe_cplx<false>, grid, dim3(kCTR), 0, st, d, row_begin, row_end, rows_pad, kb0, nkb, G);
@@ -800,11 +846,15 @@ hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t ro
   const ColSchedule c = col_schedule(M, row_begin, row_end);
   // T -> BF16 hi/lo operand (the row-pass partial planes: column stride = chunk rows)
   const int64_t rs = seg_stride / M;
-  hipLaunchKernelGGL(d.i8 ? k_col_operand<true> : k_col_operand<false>, dim3((unsigned)(c.KB / 32),
-                     (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2,
-                     row_begin, row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
+  // the int8 row pass: binary stripes (mode 1) or complex ones (mode 2, T2 the
+  // cross products)
+  const bool binary = d.n_creases == 0 && (d.levels == 0 || two_level_fast(d) || four_level_fast(d));
+  const int mode = !d.i8 ? 0 : binary ? 1 : 2;
+  hipLaunchKernelGGL(mode == 2 ? k_col_operand<2> : mode == 1 ? k_col_operand<1> : k_col_operand<0>,
+                     dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2, row_begin,
+                     row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
                      two_level_fast(d) || four_level_fast(d) ? d.S : nullptr, d.N, d.kmax,
-                     four_level_fast(d) ? (const float *)T2 : nullptr);
+                     four_level_fast(d) || mode == 2 ? (const float *)T2 : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = init_split_attributes();

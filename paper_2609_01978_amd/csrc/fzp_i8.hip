@@ -12,8 +12,11 @@
 //
 // Table layout, blocked by 64 aperture columns (one 64-byte row per column and
 // block, as the BF16 table's 32-column blocks):
-//   A8[digit][i / 64][c][i % 64],  digit 0 = v0, 1 = v1,  c = 2q + {0: re, 1: im},
-// zero for i >= N.  It occupies the first half of the split table's space.
+//   A8[t][i / 64][c][i % 64],  c = 2q + {0: re, 1: im},
+// t = 0, 1: digits v0, v1 of A; t = 2, 3: digits of A' = (-A_im, A_re) per
+// column pair, the partner that complex stripes multiply their imaginary part
+// with (the real GEMM of [S_re | S_im] and [[A_re, A_im], [-A_im, A_re]]);
+// zero for i >= N.  Four planes of 2 M Npad bytes fill the split table's space.
 
 #include <atomic>
 #include <cmath>
@@ -31,7 +34,7 @@ __global__ __launch_bounds__(256) void k_build_i8_table(InstDev d, int8_t *__res
   const int M = d.M;
   const int64_t plane = (int64_t)2 * M * d.Npad;  // bytes per digit plane
   const int64_t b8 = (i >> 6) * (int64_t)(2 * M) * 64 + (i & 63);
-  int8_t r0 = 0, r1 = 0, i0 = 0, i1 = 0;
+  int8_t r0 = 0, r1 = 0, i0 = 0, i1 = 0;  // digits of A_re, A_im
   if (i < d.N) {
     const double c = (double)i - 0.5 * (double)(d.N - 1);
     const double dq = (double)q - 0.5 * (double)M + d.sx;
@@ -50,6 +53,11 @@ __global__ __launch_bounds__(256) void k_build_i8_table(InstDev d, int8_t *__res
   A8[b8 + (int64_t)(2 * q + 1) * 64] = i0;
   A8[plane + b8 + (int64_t)(2 * q) * 64] = r1;
   A8[plane + b8 + (int64_t)(2 * q + 1) * 64] = i1;
+  // A' = (-A_im, A_re): negated digits stay digits (|v0| <= 127, |v1| <= 64)
+  A8[2 * plane + b8 + (int64_t)(2 * q) * 64] = (int8_t)(-i0);
+  A8[2 * plane + b8 + (int64_t)(2 * q + 1) * 64] = r0;
+  A8[3 * plane + b8 + (int64_t)(2 * q) * 64] = (int8_t)(-i1);
+  A8[3 * plane + b8 + (int64_t)(2 * q + 1) * 64] = r1;
 }
 
 constexpr int kTC = 128;  // real columns per tile (64 complex ROI columns), as the BF16 row pass
@@ -374,13 +382,209 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8(InstDev d, int64_t row_b
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row pass on the int8 matrix cores for complex stripes (creases, L-level
+// phase plates): T = S A with S = mask e^{i phi} per sample (Sec. 2.2, the
+// deformation map as a phase screen; Eq. 4 zones), both operands in two int8
+// digits, S = (128 s0 + s1) / s and A = (128 a0 + a1) / s, s = kI8Scale:
+//   S A s^2 = 128^2 s0 a0 + 128 (s0 a1 + s1 a0) + s1 a1,
+// the last term (at most 64^2 / s^2 = 1.5e-5) left out.  As a real GEMM,
+// [S_re | S_im] against [[A_re, A_im], [-A_im, A_re]] (the table's A and A'
+// planes), per 32 columns of K and 32 x 32 block:
+//   hi += s0_re a0 + s0_im a0',   x += s0_re a1 + s1_re a0 + s0_im a1' + s1_im a0',
+// six v_mfma_i32_32x32x32_i8 against twelve BF16 MFMAs of the three-product
+// split.  Both sums are exact in int32 per K segment (|hi| <= 2 * 127^2 * 65536,
+// |x| <= 4 * 127 * 64 * 65536, both < 2^31); hi goes to the partial planes T,
+// x to T2, and the column pass adds them as (128^2 hi + 128 x) / s^2.
+//
+// Work-group tile 256 rows x 128 real columns, 8 waves of 64 x 64 (2 x 2 MFMA
+// blocks, two sets of 64 int32 accumulators), XCD-aware order and K trimming
+// as the BF16 complex row pass; a stage is 32 columns of K: four stripe planes
+// (s0_re, s1_re, s0_im, s1_im) x 256 rows x 32 bytes and four table planes
+// (a0, a1, a0', a1') x 128 columns x 32 bytes, by direct copies into a 3-deep
+// ring, 2 stages ahead.  LDS rows are 32 bytes; the 16-byte halves of rows
+// 8 .. 15 of every 16 are swapped so that 16 rows read at one half hit 64
+// distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int kCTR8 = 256, kCTC8 = 128, kCKT8 = 32, kCRowB8 = 32;
+constexpr int kCG8 = 4 * kCTR8 * kCRowB8;     // 32768: four stripe planes
+constexpr int kCT8b = 4 * kCTC8 * kCRowB8;    // 16384: four table planes
+constexpr int kCStage8 = kCG8 + kCT8b;
+constexpr int kCRing8 = 3, kCAhead8 = 2;
+constexpr int kCLds8 = kCRing8 * kCStage8;    // 147456
+// per wave and stage: four stripe pieces and two table pieces of 1 KiB; with
+// two stages ahead the newest stage's six may stay in flight at a stage's end
+constexpr int kCWait8 = 6;
+
+__device__ __forceinline__ int chalf8(int row, int half) { return half ^ ((row >> 3) & 1); }
+
+__global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t row_begin, int64_t row_end, int n_rt,
+                                                             int n_ct, int seg_lo, int n_seg,
+                                                             const int8_t *__restrict__ G, int64_t rows_pad,
+                                                             int64_t kb0, int64_t nkb, float *__restrict__ T,
+                                                             float *__restrict__ T2, int64_t seg_stride_f) {
+  static_assert(kCWait8 == 6, "the s_waitcnt counts below");
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int Gn = n_rt * n_ct * n_seg;
+  const int slot = blockIdx.x >> 3;
+  const int g = (slot / 32) * 256 + (blockIdx.x & 7) * 32 + (slot % 32);
+  if (g >= Gn) return;
+  const int rt = g % n_rt;
+  const int ct = (g / n_rt) % n_ct;
+  const int seg = seg_lo + g / (n_rt * n_ct);
+
+  const int M2 = 2 * d.M;
+  const int64_t r0 = row_begin + (int64_t)rt * kCTR8;
+  int64_t rl = r0 + kCTR8 - 1;
+  if (rl > row_end - 1) rl = row_end - 1;
+  const int c0 = ct * kCTC8;
+  const int64_t s_lo = (int64_t)seg * d.seg_len;
+  const int64_t s_hi = s_lo + d.seg_len < d.Npad ? s_lo + d.seg_len : d.Npad;
+  int64_t k_lo, k_hi;
+  tile_chord(d, r0, rl, k_lo, k_hi);
+  k_lo = k_lo / kCKT8 * kCKT8;
+  k_hi = (k_hi + kCKT8 - 1) / kCKT8 * kCKT8;
+  if (k_lo < s_lo) k_lo = s_lo;
+  if (k_hi > s_hi) k_hi = s_hi;
+  if (k_lo < 16 * kb0) k_lo = 16 * kb0;
+  if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
+
+  // ---- copy roles.  Stripe: wave w copies pieces x = 4w .. 4w+3 (plane x / 8,
+  // rows 32 (x % 8) ..); table: pieces y = 2w, 2w+1 (plane y / 4, columns
+  // 32 (y % 4) ..).  Lane L fills LDS row L / 2, half L & 1, which holds the
+  // global half chalf8(row, L & 1): stripe block k / 16 + half, table bytes
+  // k % 64 + 16 half.  Table columns past 2M read column 0: they feed only
+  // accumulator columns that are never stored.
+  const int64_t gplane = nkb * rows_pad * 16;     // bytes per stripe plane
+  const int64_t tplane = (int64_t)M2 * d.Npad;    // bytes per table plane
+  const int8_t *gsrc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = 4 * wave + j;
+    const int row = (x & 7) * 32 + (lane >> 1);
+    gsrc[j] = G + (x >> 3) * gplane + (int64_t)chalf8(row, lane & 1) * rows_pad * 16 +
+              ((int64_t)rt * kCTR8 + row) * 16;
+  }
+  const int8_t *bsrc[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int y = 2 * wave + j;
+    const int col = (y & 3) * 32 + (lane >> 1);
+    const int gc = c0 + col < M2 ? c0 + col : 0;
+    bsrc[j] = (const int8_t *)d.A + (y >> 2) * tplane + (int64_t)gc * 64 + 16 * chalf8(col, lane & 1);
+  }
+
+  // ---- compute role: wave (wr, wc) covers rows wr*64 .., columns wc*64 ..
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int hofs = chalf8(l32, lhi) * 16;
+  const int aoff = (wr * 64 + l32) * kCRowB8 + hofs;
+  const int boff = kCG8 + (wc * 64 + l32) * kCRowB8 + hofs;
+
+  i32x16 ah[2][2], ax[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) ah[a][b][e] = ax[a][b][e] = 0;
+
+  if (k_lo < k_hi) {
+    const int64_t kb = k_lo;
+    const int nst = (int)((k_hi - k_lo) / kCKT8);
+    const int64_t klast = k_hi - kCKT8;  // copies past the end repeat the last stage
+    auto copy_stage = [&](int s) {
+      const int64_t k = kb + (int64_t)s * kCKT8 < klast ? kb + (int64_t)s * kCKT8 : klast;
+      char *dst = lds + (s % kCRing8) * kCStage8;
+      const int64_t gofs = (k / 16 - kb0) * rows_pad * 16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        __builtin_amdgcn_global_load_lds((const void *)(gsrc[j] + gofs),
+                                         (__attribute__((address_space(3))) void *)(dst + (4 * wave + j) * 1024), 16,
+                                         0, 0);
+      const int64_t tofs = (k >> 6) * M2 * 64 + (k & 63);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        __builtin_amdgcn_global_load_lds((const void *)(bsrc[j] + tofs),
+                                         (__attribute__((address_space(3))) void *)(dst + kCG8 +
+                                                                                    (2 * wave + j) * 1024),
+                                         16, 0, 0);
+    };
+    for (int s = 0; s < kCAhead8; ++s) copy_stage(s);
+    asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    for (int s = 0; s < nst; ++s) {
+      copy_stage(s + kCAhead8);
+      const char *sb = lds + (s % kCRing8) * kCStage8;
+      i32x4 b[2][4];  // [cb][a0, a1, a0', a1']
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          b[cb][t] = __builtin_bit_cast(i32x4, lds_ld16(sb + boff + t * kCTC8 * kCRowB8 + cb * 32 * kCRowB8));
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const char *pa = sb + aoff + rb * 32 * kCRowB8;
+        const i32x4 s0r = __builtin_bit_cast(i32x4, lds_ld16(pa));
+        const i32x4 s1r = __builtin_bit_cast(i32x4, lds_ld16(pa + 1 * kCTR8 * kCRowB8));
+        const i32x4 s0i = __builtin_bit_cast(i32x4, lds_ld16(pa + 2 * kCTR8 * kCRowB8));
+        const i32x4 s1i = __builtin_bit_cast(i32x4, lds_ld16(pa + 3 * kCTR8 * kCRowB8));
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          ah[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s0r, b[cb][0], ah[rb][cb], 0, 0, 0);
+          ax[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s0r, b[cb][1], ax[rb][cb], 0, 0, 0);
+          ah[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s0i, b[cb][2], ah[rb][cb], 0, 0, 0);
+          ax[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s0i, b[cb][3], ax[rb][cb], 0, 0, 0);
+          ax[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s1r, b[cb][0], ax[rb][cb], 0, 0, 0);
+          ax[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s1i, b[cb][2], ax[rb][cb], 0, 0, 0);
+        }
+      }
+      asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  // epilogue: both sums as raw int32 bits, column-major per real column, into
+  // T (hi) and T2 (cross); register v of lane l holds row 8(v/4) + 4(l/32) + v%4
+  // of its block and column l%32
+  const int64_t rs = seg_stride_f / M2;
+  const int64_t rbase = r0 + wr * 64 + 4 * lhi;
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    float *Ts = (part ? T2 : T) + (int64_t)(seg - seg_lo) * seg_stride_f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int c = c0 + wc * 64 + cb * 32 + l32;
+      if (c >= M2) continue;
+      float *col = Ts + (int64_t)c * rs - row_begin;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int64_t r = rbase + rb * 32 + 8 * a;
+          const i32x16 &v = part ? ax[rb][cb] : ah[rb][cb];
+          if (r + 3 < row_end) {
+            *(float4 *)(col + r) = make_float4(__int_as_float(v[4 * a]), __int_as_float(v[4 * a + 1]),
+                                               __int_as_float(v[4 * a + 2]), __int_as_float(v[4 * a + 3]));
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (r + e < row_end) col[r + e] = __int_as_float(v[4 * a + e]);
+          }
+        }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t init_i8_attributes() {
   static std::atomic<bool> done{false};
   if (done.load(std::memory_order_acquire)) return hipSuccess;
-  const hipError_t e =
-      hipFuncSetAttribute((const void *)k_row_pass_i8, hipFuncAttributeMaxDynamicSharedMemorySize, kLds8);
+  hipError_t e = hipFuncSetAttribute((const void *)k_row_pass_i8, hipFuncAttributeMaxDynamicSharedMemorySize, kLds8);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_row_pass_i8_cplx, hipFuncAttributeMaxDynamicSharedMemorySize, kCLds8);
   if (e == hipSuccess) done.store(true, std::memory_order_release);
   return e;
 }
@@ -424,6 +628,28 @@ hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_e
   const int64_t grid = (G + 255) / 256 * 256;  // whole rounds of 32 work-groups on each of 8 XCDs
   hipLaunchKernelGGL(k_row_pass_i8, dim3((unsigned)grid), dim3(512), kLds8, st, d, row_begin, row_end, n_rt, n_ct,
                      seg_lo, n_seg, bits, bits_rows_pad(rows), (float *)T, 2 * seg_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, float2 *T2,
+                                   int64_t seg_stride, const void *G, hipStream_t st) {
+  const int64_t rows = row_end - row_begin;
+  if (rows <= 0) return hipSuccess;
+  int64_t rows_pad, kb0, nkb;
+  split_stripe_extent(d, row_begin, row_end, rows_pad, kb0, nkb);
+  int seg_lo, seg_hi;
+  split_seg_range(d, row_begin, row_end, seg_lo, seg_hi);
+  if (seg_hi <= seg_lo || nkb <= 0) return hipSuccess;
+  hipError_t e = init_i8_attributes();
+  if (e != hipSuccess) return e;
+  const int n_rt = (int)((rows + kCTR8 - 1) / kCTR8);
+  const int n_ct = (2 * d.M + kCTC8 - 1) / kCTC8;
+  const int n_seg = seg_hi - seg_lo;
+  const int64_t Gn = (int64_t)n_rt * n_ct * n_seg;
+  const int64_t grid = (Gn + 255) / 256 * 256;  // whole rounds of 32 work-groups on each of 8 XCDs
+  hipLaunchKernelGGL(k_row_pass_i8_cplx, dim3((unsigned)grid), dim3(512), kCLds8, st, d, row_begin, row_end, n_rt,
+                     n_ct, seg_lo, n_seg, (const int8_t *)G, rows_pad, kb0, nkb, (float *)T, (float *)T2,
+                     2 * seg_stride);
   return hipGetLastError();
 }
 

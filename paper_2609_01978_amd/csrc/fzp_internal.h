@@ -204,6 +204,13 @@ hipError_t launch_mask_bits_i8(const InstDev &d, int64_t row_begin, int64_t row_
                                uint32_t *bits2 = nullptr);
 hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
                               const uint32_t *bits, hipStream_t st);
+// Complex stripes on the int8 matrix cores (launch_stripe_cplx writes their
+// int8 digit planes when d.i8): the digit-0 products into T, the cross
+// products into T2, both laid out as launch_row_pass_split's partials.
+void split_stripe_extent(const InstDev &d, int64_t row_begin, int64_t row_end, int64_t &rows_pad, int64_t &kb0,
+                         int64_t &nkb);
+hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, float2 *T2,
+                                   int64_t seg_stride, const void *G, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,
                            hipStream_t st);  // FP64 path
 // Split path column pass as a split-BF16 GEMM (fzp_cplx.hip): the column kernel

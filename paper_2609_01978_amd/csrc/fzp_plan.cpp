@@ -375,13 +375,13 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         if (ap->levels == 4 && ih.in.n_creases == 0) p.mask_sets = 2;
       }
     if (o.flags & FZP_FLAG_SPLIT_INT8) {
-      if (!split || cplx) {
+      if (!split) {
         delete h;
-        return fail(FZP_E_UNSUPPORTED,
-                    "fzp_plan: FZP_FLAG_SPLIT_INT8 needs the split path and crease-free amplitude, 2- or 4-level "
-                    "plates");
+        return fail(FZP_E_UNSUPPORTED, "fzp_plan: FZP_FLAG_SPLIT_INT8 needs the split path");
       }
       for (auto &ih : p.inst) ih.dev.i8 = 1;
+      // complex stripes on the int8 row pass write two sets of partial planes
+      if (cplx) p.mask_sets = 2;
     }
     if (split)
       for (const auto &ih : p.inst)
@@ -828,7 +828,8 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
   const bool cplx = split && (ih.dev.n_creases > 0 ||
                               (ih.dev.levels != 0 && !fzp::two_level_fast(ih.dev) && !four));
   void *T = ws + p.off_T[lane];
-  void *T2 = four ? ws + p.off_T[lane] + p.T_bytes : nullptr;  // the second mask's partial planes
+  // the second mask's partial planes, or the int8 complex row pass's cross products
+  void *T2 = four || (cplx && ih.dev.i8) ? ws + p.off_T[lane] + p.T_bytes : nullptr;
   const size_t bits_set = (size_t)p.mask_sets * p.bits_bytes;   // one operand buffer
   hipError_t e;
   // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples
@@ -924,7 +925,10 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     }
     e = begin_mark(st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
-    if (cplx)
+    if (cplx && ih.dev.i8)
+      e = fzp::launch_row_pass_i8_cplx(ih.dev, r0, r1, (float2 *)T, (float2 *)T2, seg_stride,
+                                       ws + p.off_G[lane] + b * p.G_bytes, st);
+    else if (cplx)
       e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride,
                                           (const uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), st);
     else if (split) {
@@ -1387,7 +1391,7 @@ extern "C" fzp_status_t fzp_autotune(fzp_plan_t h, void *workspace, double *roi_
       }
       std::vector<int32_t> bs{p.bin_variant}, cs{p.cplx_variant};
       if (binary && !p.inst[0].dev.i8) bs = {0, 1, 2, 3, 4};  // the int8 row pass has one form
-      if (cplx) cs = {0, 1, 2};
+      if (cplx && !p.inst[0].dev.i8) cs = {0, 1, 2};  // the int8 complex row pass has one form
       tiles.clear();
       for (int32_t c : cs)
         for (int32_t b : bs) tiles.push_back(b + 8 * c);

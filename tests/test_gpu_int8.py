@@ -1,14 +1,15 @@
 """GPU parity of the int8 row pass (FZP_FLAG_SPLIT_INT8) through the C ABI
 against the FP64 oracle.
 
-The int8 form holds the kernel row in fixed point of step 1/16256 (at most
-3.1e-5 per component) and sums the masked products exactly in int32; the
-column pass is the split path's.  Bar: complex and intensity rel-L2 <= 1e-4,
-as for the split-BF16 path (the quantisation is incoherent over the aperture:
-measured errors are near 1e-6).  Cases: ragged row and column tiles with
-several K stages and segments, 2- and 4-level phase plates (prefix sums minus
-binary GEMMs), rows that miss the disc, and sampled stripes of the 1 m
-element at full size.
+The int8 form holds the kernel row (and a complex stripe) in fixed point of
+step 1/16256 (at most 3.1e-5 per component) and sums the products exactly in
+int32; the column pass is the split path's.  Bar: complex and intensity
+rel-L2 <= 1e-4, as for the split-BF16 path (the quantisation is incoherent
+over the aperture: measured errors are near 1e-6).  Cases: ragged row and
+column tiles with several K stages and segments, 2- and 4-level phase plates
+(prefix sums minus binary GEMMs), rows that miss the disc, sampled stripes of
+the 1 m element at full size, and complex stripes: creases, 3- and 8-level
+plates, creases on a 4-level plate over several chunks, a mixed graph batch.
 """
 import numpy as np
 import pytest
@@ -17,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 import paper_2609_01978_amd as P  # noqa: E402
 from oracle import fzp_oracle as O  # noqa: E402
-from fzp_inputs import workload  # noqa: E402
+from fzp_inputs import crease_draws, workload  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 LAM0 = 632.8e-9
@@ -46,7 +47,7 @@ def oracle(ap, inst):
     a = O.Aperture(D=ap["D"], f0=ap["f0"], lambda0=ap["lambda0"], N=ap["N"], levels=ap.get("levels", 0),
                    centre_open=ap.get("centre_open", 0))
     i = O.Instance(lam=inst["lam"], M=inst["M"], x0=inst.get("x0", 0.0), y0=inst.get("y0", 0.0),
-                   half_width=inst.get("half_width", 0.0))
+                   half_width=inst.get("half_width", 0.0), creases=inst.get("creases"))
     return a, i
 
 
@@ -105,4 +106,58 @@ def test_fzp1m_sampled_stripes_int8():
         ref = O.propagate(a, i, method="bluestein", rows=(j0, j0 + S), stripe=32)
         e = rel_l2(U, ref)
         announce(f"  complex rel-L2 {e:.3e}")
+        assert e <= 1e-4
+
+
+CPLX = {
+    "creases": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=1536),
+                dict(lam=700e-9, M=96, creases=crease_draws(5, 2e-3, LAM0, 8) * np.array([1, 1, 0.2, 1])), 0),
+    "levels3_ragged": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=1999, levels=3), dict(lam=600e-9, M=64, x0=1e-6), 0),
+    "levels8": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096, levels=8), dict(lam=600e-9, M=256), 0),
+    "creased_4level_chunks": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=3001, levels=4),
+                              dict(lam=700e-9, M=272,
+                                   creases=crease_draws(21, 2e-3, LAM0, 6) * np.array([1, 1, 0.3, 1])), 700),
+}
+
+
+@pytest.mark.parametrize("case", list(CPLX))
+def test_int8_complex_stripes_full_roi(case):
+    ap, inst, chunk = CPLX[case]
+    announce(f"complex stripes {case}: N={ap['N']} M={inst['M']} levels={ap.get('levels', 0)} chunk {chunk}")
+    _, _, _, U8 = run(ap, inst, path="split", int8=True, allow_undersampled=True, chunk_rows=chunk)
+    _, _, _, Ub = run(ap, inst, path="split", allow_undersampled=True, chunk_rows=chunk)
+    ref = O.propagate(*oracle(ap, inst), stripe=512)
+    e8, eb = rel_l2(U8, ref), rel_l2(Ub, ref)
+    ei = rel_l2(O.intensity(U8), O.intensity(ref))
+    announce(f"  int8 complex {e8:.2e} intensity {ei:.2e}; BF16 split complex {eb:.2e}")
+    assert e8 <= 1e-4 and ei <= 1e-4
+
+
+def test_int8_mixed_batch_graph_matches_eager_and_oracle():
+    """Binary and creased instances of mixed ROI sizes in one plan on two
+    lanes: the captured graph equals the eager propagation bit for bit (int8
+    sums are exact and the column pass is deterministic), and each instance
+    is within the bar of the oracle."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048)
+    cr = crease_draws(9, 2e-3, LAM0, 8) * np.array([1, 1, 0.2, 1])
+    insts = [dict(lam=LAM0, M=64), dict(lam=560e-9, M=128, creases=cr), dict(lam=700e-9, M=96, creases=cr[:3])]
+    plan = P.Plan(ap, insts, path="split", int8=True, lanes=2, chunk_rows=512)
+    ws, roi = plan.alloc()
+    plan.propagate(ws, roi)
+    torch.cuda.synchronize()
+    eager = roi.clone()
+    g = plan.graph(ws, roi)
+    other = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        roi.fill_(float("nan"))
+        other.add_(1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(roi, eager), rep
+    for k, inst in enumerate(insts):
+        U = plan.roi_view(roi, k).cpu().numpy()
+        ref = O.propagate(*oracle(ap, inst), stripe=512)
+        e = rel_l2(U, ref)
+        announce(f"  batch instance {k} M={inst['M']} creased={'creases' in inst} complex rel-L2 {e:.2e}")
         assert e <= 1e-4
