@@ -513,9 +513,8 @@ __device__ __forceinline__ int64_t sum_segments_i32(const float *src, int nseg, 
 }
 
 // MODE 0: float32 planes (split-BF16 row pass); 1: int32 sums of the int8
-// binary row pass, in units of 1 / kI8Scale; 2: the int8 complex row pass, T
-// the digit-0 products and T2 the cross products, in units of 1 / kI8Scale^2
-// after weighting 128^2 and 128.
+// binary row pass, in units of 1 / kI8Scale; 2: float32 planes of the int8
+// complex row pass, in units of 1 / kI8Scale^2.
 template <int MODE> __device__ __forceinline__ double sum_segments(const float *src, int nseg, int64_t seg_stride_f) {
   if constexpr (MODE == 1) return (double)sum_segments_i32(src, nseg, seg_stride_f) * (1.0 / kI8Scale);
   double v = 0.0;
@@ -544,15 +543,9 @@ __global__ __launch_bounds__(256) void k_col_operand(int M2, int64_t row_begin, 
   const int64_t j = kB0 + kk;
   uint16_t h = 0, l = 0;
   if (j >= row_begin && j < row_end) {
-    double v;
-    if constexpr (MODE == 2) {
-      const int64_t hi = sum_segments_i32(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-      const int64_t x = sum_segments_i32(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-      v = (double)(16384 * hi + 128 * x) * (1.0 / (kI8Scale * kI8Scale));
-    } else {
-      v = sum_segments<MODE>(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
-    }
-    if (MODE != 2 && T2) {
+    double v = sum_segments<MODE == 2 ? 0 : MODE>(T + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
+    if constexpr (MODE == 2) v *= 1.0 / (kI8Scale * kI8Scale);
+    if (T2) {
       // c and its partner column c ^ 1 (re / im of the same ROI column)
       const double u_o = sum_segments<MODE>(T + (int64_t)(c ^ 1) * rs + (j - row_begin), nseg, seg_stride_f);
       const double v_s = sum_segments<MODE>(T2 + (int64_t)c * rs + (j - row_begin), nseg, seg_stride_f);
@@ -846,15 +839,14 @@ hipError_t launch_col_pass_split(const InstDev &d, int64_t row_begin, int64_t ro
   const ColSchedule c = col_schedule(M, row_begin, row_end);
   // T -> BF16 hi/lo operand (the row-pass partial planes: column stride = chunk rows)
   const int64_t rs = seg_stride / M;
-  // the int8 row pass: binary stripes (mode 1) or complex ones (mode 2, T2 the
-  // cross products)
+  // the int8 row pass: binary stripes (mode 1) or complex ones (mode 2)
   const bool binary = d.n_creases == 0 && (d.levels == 0 || two_level_fast(d) || four_level_fast(d));
   const int mode = !d.i8 ? 0 : binary ? 1 : 2;
   hipLaunchKernelGGL(mode == 2 ? k_col_operand<2> : mode == 1 ? k_col_operand<1> : k_col_operand<0>,
                      dim3((unsigned)(c.KB / 32), (unsigned)((M2 + 7) / 8)), dim3(256), 0, st, M2, row_begin,
                      row_end, (const float *)T, nseg, 2 * seg_stride, rs, c.kB0, c.KB, Tb,
                      two_level_fast(d) || four_level_fast(d) ? d.S : nullptr, d.N, d.kmax,
-                     four_level_fast(d) || mode == 2 ? (const float *)T2 : nullptr);
+                     four_level_fast(d) ? (const float *)T2 : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = init_split_attributes();

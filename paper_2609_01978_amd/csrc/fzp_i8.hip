@@ -12,11 +12,8 @@
 //
 // Table layout, blocked by 64 aperture columns (one 64-byte row per column and
 // block, as the BF16 table's 32-column blocks):
-//   A8[t][i / 64][c][i % 64],  c = 2q + {0: re, 1: im},
-// t = 0, 1: digits v0, v1 of A; t = 2, 3: digits of A' = (-A_im, A_re) per
-// column pair, the partner that complex stripes multiply their imaginary part
-// with (the real GEMM of [S_re | S_im] and [[A_re, A_im], [-A_im, A_re]]);
-// zero for i >= N.  Four planes of 2 M Npad bytes fill the split table's space.
+//   A8[digit][i / 64][c][i % 64],  digit 0 = v0, 1 = v1,  c = 2q + {0: re, 1: im},
+// zero for i >= N.  It occupies the first half of the split table's space.
 
 #include <atomic>
 #include <cmath>
@@ -53,11 +50,6 @@ __global__ __launch_bounds__(256) void k_build_i8_table(InstDev d, int8_t *__res
   A8[b8 + (int64_t)(2 * q + 1) * 64] = i0;
   A8[plane + b8 + (int64_t)(2 * q) * 64] = r1;
   A8[plane + b8 + (int64_t)(2 * q + 1) * 64] = i1;
-  // A' = (-A_im, A_re): negated digits stay digits (|v0| <= 127, |v1| <= 64)
-  A8[2 * plane + b8 + (int64_t)(2 * q) * 64] = (int8_t)(-i0);
-  A8[2 * plane + b8 + (int64_t)(2 * q + 1) * 64] = r0;
-  A8[3 * plane + b8 + (int64_t)(2 * q) * 64] = (int8_t)(-i1);
-  A8[3 * plane + b8 + (int64_t)(2 * q + 1) * 64] = r1;
 }
 
 constexpr int kTC = 128;  // real columns per tile (64 complex ROI columns), as the BF16 row pass
@@ -389,41 +381,60 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8(InstDev d, int64_t row_b
 // digits, S = (128 s0 + s1) / s and A = (128 a0 + a1) / s, s = kI8Scale:
 //   S A s^2 = 128^2 s0 a0 + 128 (s0 a1 + s1 a0) + s1 a1,
 // the last term (at most 64^2 / s^2 = 1.5e-5) left out.  As a real GEMM,
-// [S_re | S_im] against [[A_re, A_im], [-A_im, A_re]] (the table's A and A'
-// planes), per 32 columns of K and 32 x 32 block:
+// [S_re | S_im] against [[A_re, A_im], [-A_im, A_re]]: the lower block A' is
+// not stored but made in registers from the upper one, column n's operand
+// from column n ^ 1 (the neighbouring lane) negated on even columns (negated
+// digits stay digits: |v0| <= 127, |v1| <= 64).  Per 32 columns of K and
+// 32 x 32 block:
 //   hi += s0_re a0 + s0_im a0',   x += s0_re a1 + s1_re a0 + s0_im a1' + s1_im a0',
 // six v_mfma_i32_32x32x32_i8 against twelve BF16 MFMAs of the three-product
 // split.  Both sums are exact in int32 per K segment (|hi| <= 2 * 127^2 * 65536,
-// |x| <= 4 * 127 * 64 * 65536, both < 2^31); hi goes to the partial planes T,
-// x to T2, and the column pass adds them as (128^2 hi + 128 x) / s^2.
+// |x| <= 4 * 127 * 64 * 65536, both < 2^31); the epilogue forms 128^2 hi + 128 x
+// exactly in int64 and stores it rounded once to float32 (relative 6e-8) in
+// the partial planes T, which the column pass adds in float64 and scales by
+// 1 / s^2.
 //
 // Work-group tile 256 rows x 128 real columns, 8 waves of 64 x 64 (2 x 2 MFMA
 // blocks, two sets of 64 int32 accumulators), XCD-aware order and K trimming
 // as the BF16 complex row pass; a stage is 32 columns of K: four stripe planes
-// (s0_re, s1_re, s0_im, s1_im) x 256 rows x 32 bytes and four table planes
-// (a0, a1, a0', a1') x 128 columns x 32 bytes, by direct copies into a 3-deep
-// ring, 2 stages ahead.  LDS rows are 32 bytes; the 16-byte halves of rows
+// (s0_re, s1_re, s0_im, s1_im) x 256 rows x 32 bytes and two table planes
+// (a0, a1) x 128 columns x 32 bytes, by direct copies into a 3-deep ring, 2
+// stages ahead.  LDS rows are 32 bytes; the 16-byte halves of rows
 // 8 .. 15 of every 16 are swapped so that 16 rows read at one half hit 64
 // distinct banks.
 // ---------------------------------------------------------------------------
 constexpr int kCTR8 = 256, kCTC8 = 128, kCKT8 = 32, kCRowB8 = 32;
 constexpr int kCG8 = 4 * kCTR8 * kCRowB8;     // 32768: four stripe planes
-constexpr int kCT8b = 4 * kCTC8 * kCRowB8;    // 16384: four table planes
+constexpr int kCT8b = 2 * kCTC8 * kCRowB8;    // 8192: two table planes
 constexpr int kCStage8 = kCG8 + kCT8b;
 constexpr int kCRing8 = 3, kCAhead8 = 2;
-constexpr int kCLds8 = kCRing8 * kCStage8;    // 147456
-// per wave and stage: four stripe pieces and two table pieces of 1 KiB; with
-// two stages ahead the newest stage's six may stay in flight at a stage's end
-constexpr int kCWait8 = 6;
+constexpr int kCLds8 = kCRing8 * kCStage8;    // 122880
+// per wave and stage: four stripe pieces and one table piece of 1 KiB; with
+// two stages ahead the newest stage's five may stay in flight at a stage's end
+constexpr int kCWait8 = 5;
 
 __device__ __forceinline__ int chalf8(int row, int half) { return half ^ ((row >> 3) & 1); }
+
+// Column n's B operand from lane l ^ 1 (column n ^ 1, the same K half), each
+// byte negated on even columns: -b = ((0x80 - (b & 0x7f)) ^ 0x80) ^ (b & 0x80)
+// per byte, with no carry between bytes.
+__device__ __forceinline__ i32x4 swap_neg_i8(i32x4 b, bool even) {
+  i32x4 r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t u = (uint32_t)__builtin_amdgcn_mov_dpp(b[j], 0xb1, 0xf, 0xf, true);  // quad_perm [1,0,3,2]
+    const uint32_t n = ((0x80808080u - (u & 0x7f7f7f7fu)) ^ 0x80808080u) ^ (u & 0x80808080u);
+    r[j] = (int32_t)(even ? n : u);
+  }
+  return r;
+}
 
 __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t row_begin, int64_t row_end, int n_rt,
                                                              int n_ct, int seg_lo, int n_seg,
                                                              const int8_t *__restrict__ G, int64_t rows_pad,
                                                              int64_t kb0, int64_t nkb, float *__restrict__ T,
-                                                             float *__restrict__ T2, int64_t seg_stride_f) {
-  static_assert(kCWait8 == 6, "the s_waitcnt counts below");
+                                                             int64_t seg_stride_f) {
+  static_assert(kCWait8 == 5, "the s_waitcnt counts below");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -453,8 +464,7 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
   if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
 
   // ---- copy roles.  Stripe: wave w copies pieces x = 4w .. 4w+3 (plane x / 8,
-  // rows 32 (x % 8) ..); table: pieces y = 2w, 2w+1 (plane y / 4, columns
-  // 32 (y % 4) ..).  Lane L fills LDS row L / 2, half L & 1, which holds the
+  // rows 32 (x % 8) ..); table: piece w (plane w / 4, columns 32 (w % 4) ..).  Lane L fills LDS row L / 2, half L & 1, which holds the
   // global half chalf8(row, L & 1): stripe block k / 16 + half, table bytes
   // k % 64 + 16 half.  Table columns past 2M read column 0: they feed only
   // accumulator columns that are never stored.
@@ -468,13 +478,11 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
     gsrc[j] = G + (x >> 3) * gplane + (int64_t)chalf8(row, lane & 1) * rows_pad * 16 +
               ((int64_t)rt * kCTR8 + row) * 16;
   }
-  const int8_t *bsrc[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int y = 2 * wave + j;
-    const int col = (y & 3) * 32 + (lane >> 1);
+  const int8_t *bsrc;
+  {
+    const int col = (wave & 3) * 32 + (lane >> 1);
     const int gc = c0 + col < M2 ? c0 + col : 0;
-    bsrc[j] = (const int8_t *)d.A + (y >> 2) * tplane + (int64_t)gc * 64 + 16 * chalf8(col, lane & 1);
+    bsrc = (const int8_t *)d.A + (wave >> 2) * tplane + (int64_t)gc * 64 + 16 * chalf8(col, lane & 1);
   }
 
   // ---- compute role: wave (wr, wc) covers rows wr*64 .., columns wc*64 ..
@@ -483,6 +491,7 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
   const int hofs = chalf8(l32, lhi) * 16;
   const int aoff = (wr * 64 + l32) * kCRowB8 + hofs;
   const int boff = kCG8 + (wc * 64 + l32) * kCRowB8 + hofs;
+  const bool even = (lane & 1) == 0;
 
   i32x16 ah[2][2], ax[2][2];
 #pragma unroll
@@ -506,24 +515,24 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
                                          (__attribute__((address_space(3))) void *)(dst + (4 * wave + j) * 1024), 16,
                                          0, 0);
       const int64_t tofs = (k >> 6) * M2 * 64 + (k & 63);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        __builtin_amdgcn_global_load_lds((const void *)(bsrc[j] + tofs),
-                                         (__attribute__((address_space(3))) void *)(dst + kCG8 +
-                                                                                    (2 * wave + j) * 1024),
-                                         16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(bsrc + tofs),
+                                       (__attribute__((address_space(3))) void *)(dst + kCG8 + wave * 1024), 16, 0,
+                                       0);
     };
     for (int s = 0; s < kCAhead8; ++s) copy_stage(s);
-    asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    asm volatile("s_waitcnt vmcnt(5) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     for (int s = 0; s < nst; ++s) {
       copy_stage(s + kCAhead8);
       const char *sb = lds + (s % kCRing8) * kCStage8;
       i32x4 b[2][4];  // [cb][a0, a1, a0', a1']
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 2; ++t)
           b[cb][t] = __builtin_bit_cast(i32x4, lds_ld16(sb + boff + t * kCTC8 * kCRowB8 + cb * 32 * kCRowB8));
+        b[cb][2] = swap_neg_i8(b[cb][0], even);
+        b[cb][3] = swap_neg_i8(b[cb][1], even);
+      }
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
         const char *pa = sb + aoff + rb * 32 * kCRowB8;
@@ -541,39 +550,38 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
           ax[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(s1i, b[cb][2], ax[rb][cb], 0, 0, 0);
         }
       }
-      asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      asm volatile("s_waitcnt vmcnt(5) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
-  // epilogue: both sums as raw int32 bits, column-major per real column, into
-  // T (hi) and T2 (cross); register v of lane l holds row 8(v/4) + 4(l/32) + v%4
-  // of its block and column l%32
+  // epilogue: 128^2 hi + 128 x per element, column-major per real column;
+  // register v of lane l holds row 8(v/4) + 4(l/32) + v%4 of its block and
+  // column l%32
   const int64_t rs = seg_stride_f / M2;
   const int64_t rbase = r0 + wr * 64 + 4 * lhi;
+  float *Ts = T + (int64_t)(seg - seg_lo) * seg_stride_f;
+  auto val = [&](int rb, int cb, int e) {
+    return (float)(16384 * (int64_t)ah[rb][cb][e] + 128 * (int64_t)ax[rb][cb][e]);
+  };
 #pragma unroll
-  for (int part = 0; part < 2; ++part) {
-    float *Ts = (part ? T2 : T) + (int64_t)(seg - seg_lo) * seg_stride_f;
+  for (int cb = 0; cb < 2; ++cb) {
+    const int c = c0 + wc * 64 + cb * 32 + l32;
+    if (c >= M2) continue;
+    float *col = Ts + (int64_t)c * rs - row_begin;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int c = c0 + wc * 64 + cb * 32 + l32;
-      if (c >= M2) continue;
-      float *col = Ts + (int64_t)c * rs - row_begin;
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int a = 0; a < 4; ++a) {
+        const int64_t r = rbase + rb * 32 + 8 * a;
+        if (r + 3 < row_end) {
+          *(float4 *)(col + r) = make_float4(val(rb, cb, 4 * a), val(rb, cb, 4 * a + 1), val(rb, cb, 4 * a + 2),
+                                             val(rb, cb, 4 * a + 3));
+        } else {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int64_t r = rbase + rb * 32 + 8 * a;
-          const i32x16 &v = part ? ax[rb][cb] : ah[rb][cb];
-          if (r + 3 < row_end) {
-            *(float4 *)(col + r) = make_float4(__int_as_float(v[4 * a]), __int_as_float(v[4 * a + 1]),
-                                               __int_as_float(v[4 * a + 2]), __int_as_float(v[4 * a + 3]));
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (r + e < row_end) col[r + e] = __int_as_float(v[4 * a + e]);
-          }
+          for (int e = 0; e < 4; ++e)
+            if (r + e < row_end) col[r + e] = val(rb, cb, 4 * a + e);
         }
-    }
+      }
   }
 }
 
@@ -631,7 +639,7 @@ hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_e
   return hipGetLastError();
 }
 
-hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, float2 *T2,
+hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T,
                                    int64_t seg_stride, const void *G, hipStream_t st) {
   const int64_t rows = row_end - row_begin;
   if (rows <= 0) return hipSuccess;
@@ -648,8 +656,7 @@ hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t 
   const int64_t Gn = (int64_t)n_rt * n_ct * n_seg;
   const int64_t grid = (Gn + 255) / 256 * 256;  // whole rounds of 32 work-groups on each of 8 XCDs
   hipLaunchKernelGGL(k_row_pass_i8_cplx, dim3((unsigned)grid), dim3(512), kCLds8, st, d, row_begin, row_end, n_rt,
-                     n_ct, seg_lo, n_seg, (const int8_t *)G, rows_pad, kb0, nkb, (float *)T, (float *)T2,
-                     2 * seg_stride);
+                     n_ct, seg_lo, n_seg, (const int8_t *)G, rows_pad, kb0, nkb, (float *)T, 2 * seg_stride);
   return hipGetLastError();
 }
 

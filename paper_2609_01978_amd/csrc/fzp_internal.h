@@ -205,11 +205,11 @@ hipError_t launch_mask_bits_i8(const InstDev &d, int64_t row_begin, int64_t row_
 hipError_t launch_row_pass_i8(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, int64_t seg_stride,
                               const uint32_t *bits, hipStream_t st);
 // Complex stripes on the int8 matrix cores (launch_stripe_cplx writes their
-// int8 digit planes when d.i8): the digit-0 products into T, the cross
-// products into T2, both laid out as launch_row_pass_split's partials.
+// int8 digit planes when d.i8): partials laid out as launch_row_pass_split's,
+// in units of 1 / kI8Scale^2.
 void split_stripe_extent(const InstDev &d, int64_t row_begin, int64_t row_end, int64_t &rows_pad, int64_t &kb0,
                          int64_t &nkb);
-hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T, float2 *T2,
+hipError_t launch_row_pass_i8_cplx(const InstDev &d, int64_t row_begin, int64_t row_end, float2 *T,
                                    int64_t seg_stride, const void *G, hipStream_t st);
 hipError_t launch_col_pass(const InstDev &d, int64_t row_begin, int64_t row_end, const double2 *T, double2 *roi,
                            hipStream_t st);  // FP64 path

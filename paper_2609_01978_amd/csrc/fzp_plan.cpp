@@ -380,8 +380,6 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
         return fail(FZP_E_UNSUPPORTED, "fzp_plan: FZP_FLAG_SPLIT_INT8 needs the split path");
       }
       for (auto &ih : p.inst) ih.dev.i8 = 1;
-      // complex stripes on the int8 row pass write two sets of partial planes
-      if (cplx) p.mask_sets = 2;
     }
     if (split)
       for (const auto &ih : p.inst)
@@ -828,8 +826,7 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
   const bool cplx = split && (ih.dev.n_creases > 0 ||
                               (ih.dev.levels != 0 && !fzp::two_level_fast(ih.dev) && !four));
   void *T = ws + p.off_T[lane];
-  // the second mask's partial planes, or the int8 complex row pass's cross products
-  void *T2 = four || (cplx && ih.dev.i8) ? ws + p.off_T[lane] + p.T_bytes : nullptr;
+  void *T2 = four ? ws + p.off_T[lane] + p.T_bytes : nullptr;  // the second mask's partial planes
   const size_t bits_set = (size_t)p.mask_sets * p.bits_bytes;   // one operand buffer
   hipError_t e;
   // the chunks (aligned to multiples of chunk_rows from row 0) with disc samples
@@ -926,8 +923,8 @@ fzp_status_t enqueue_instance(Plan &p, InstHost &ih, int lane, char *ws, double2
     e = begin_mark(st);
     if (e != hipSuccess) return hip_fail("fzp_propagate_roi_range: event", e);
     if (cplx && ih.dev.i8)
-      e = fzp::launch_row_pass_i8_cplx(ih.dev, r0, r1, (float2 *)T, (float2 *)T2, seg_stride,
-                                       ws + p.off_G[lane] + b * p.G_bytes, st);
+      e = fzp::launch_row_pass_i8_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride, ws + p.off_G[lane] + b * p.G_bytes,
+                                       st);
     else if (cplx)
       e = fzp::launch_row_pass_split_cplx(ih.dev, r0, r1, (float2 *)T, seg_stride,
                                           (const uint16_t *)(ws + p.off_G[lane] + b * p.G_bytes), st);
