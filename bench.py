@@ -345,8 +345,9 @@ def run_multilevel(args, dev, levels=None):
 
 def run_configs(dev, steps: int = 3):
     """The 2 mm (N = 4096, M = 256) and 20 mm (N = 32768, M = 1024) elements on
-    both paths: whole-aperture propagation plus metrics per step, after one
-    warm-up step; split intensity against the FP64 path's."""
+    both paths and the int8 row pass: whole-aperture propagation plus metrics
+    per step, after one warm-up step; split intensities against the FP64
+    path's."""
     import numpy as np
     import torch
     import paper_2609_01978_amd as P
@@ -358,8 +359,9 @@ def run_configs(dev, steps: int = 3):
         inst = dict(lam=w["lambda0"], M=w["M"])
         samples = float(w["N"]) ** 2
         res, I = {}, {}
-        for path in ("split", "fp64"):
-            plan = P.Plan(ap, [inst], path=path, stripe_rows=w["stripe"] if path == "split" else 0)
+        for path in ("split", "split_int8", "fp64"):
+            plan = P.Plan(ap, [inst], path="fp64" if path == "fp64" else "split",
+                          stripe_rows=0 if path == "fp64" else w["stripe"], int8=path == "split_int8")
             ws, roi = plan.alloc(dev)
             plan.propagate(ws, roi)
             plan.metrics(ws, roi)
@@ -376,9 +378,15 @@ def run_configs(dev, steps: int = 3):
             del ws, roi, plan
             torch.cuda.empty_cache()
         e = float(np.linalg.norm(I["split"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
-        log(f"{name}: split {res['split']['ms_per_step']} ms, fp64 {res['fp64']['ms_per_step']} ms, rel-L2 {e:.2e}")
+        e8 = float(np.linalg.norm(I["split_int8"] - I["fp64"]) / np.linalg.norm(I["fp64"]))
+        log(f"{name}: split {res['split']['ms_per_step']} ms, int8 {res['split_int8']['ms_per_step']} ms, "
+            f"fp64 {res['fp64']['ms_per_step']} ms, rel-L2 {e:.2e} / {e8:.2e}")
+        res["split_int8"].update({"rel_l2_vs_fp64": e8, "valid_rel_l2_le_1e-4": e8 <= 1e-4,
+                                  "speedup_vs_fp64": round(res["fp64"]["ms_per_step"] /
+                                                           res["split_int8"]["ms_per_step"], 3)})
         out[name] = {"workload": f"binary FZP D={w['D']} m f/5 lambda=632.8 nm, N={w['N']}^2, ROI {w['M']}^2",
                      "steps": steps, "split_bf16": res["split"], "fp64_bluestein": res["fp64"],
+                     "split_int8": res["split_int8"],
                      "rel_l2_split_vs_fp64": e, "valid_rel_l2_le_1e-4": e <= 1e-4,
                      "speedup_split_vs_fp64": round(res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"], 3)}
     return out
