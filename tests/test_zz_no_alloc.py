@@ -22,12 +22,14 @@ def announce(msg):
 
 def plans(path):
     """A larger plan (N = 4096, ROIs 256 and 128, one creased) and a smaller
-    one (N = 2048, one ROI of 64), both within FZP_STATIC_SCRATCH_BYTES."""
+    one (N = 2048, one ROI of 64), both within FZP_STATIC_SCRATCH_BYTES;
+    "split_int8" is the split path with the int8 row pass."""
+    kw = dict(path="split", int8=True) if path == "split_int8" else dict(path=path)
     big = P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=4096),
                  [dict(lam=LAM0, M=256), dict(lam=560e-9, M=128, creases=crease_draws(7, 2e-3, LAM0, 8))],
-                 path=path, chunk_rows=512)
+                 chunk_rows=512, **kw)
     small = P.Plan(dict(D=1e-3, f0=5e-3, lambda0=LAM0, N=2048), [dict(lam=700e-9, M=64, x0=1e-6)],
-                   path=path, chunk_rows=512)
+                   chunk_rows=512, **kw)
     for p in (big, small):
         assert p.workspace_size <= L.STATIC_SCRATCH_BYTES
     return big, small
@@ -45,7 +47,7 @@ def test_oversized_plan_is_refused_before_any_device_call():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("path,tol", [("fp64", 1e-9), ("split", 1e-4)])
+@pytest.mark.parametrize("path,tol", [("fp64", 1e-9), ("split", 1e-4), ("split_int8", 1e-4)])
 def test_static_workspace_matches_caller_workspace(path, tol):
     torch = pytest.importorskip("torch")
     big, small = plans(path)
