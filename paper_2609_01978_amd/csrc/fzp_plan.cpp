@@ -1334,6 +1334,7 @@ std::string tune_key(const Plan &p) {
   k << "fzp1/" << arch << "/N" << p.ap.N << "/path" << p.opt.path << "/chunk" << p.chunk_rows << "/L"
     << p.lanes_max;
   if (p.ap.levels != 0) k << "/phase" << p.ap.levels;
+  if (!p.inst.empty() && p.inst[0].dev.i8) k << "/i8";  // the int8 row pass times differently
   // the multiset of (M, deformed) over instances, in instance order
   for (const auto &ih : p.inst) k << "/" << ih.dev.M << (ih.dev.n_creases > 0 ? "c" : "f");
   return k.str();

@@ -161,3 +161,40 @@ def test_int8_mixed_batch_graph_matches_eager_and_oracle():
         e = rel_l2(U, ref)
         announce(f"  batch instance {k} M={inst['M']} creased={'creases' in inst} complex rel-L2 {e:.2e}")
         assert e <= 1e-4
+
+
+def test_int8_binary_sums_do_not_depend_on_the_schedule(tmp_path):
+    """The int8 binary row pass sums exactly (int32 per K segment, int64 over
+    segments), so its partial sums, and with them the ROI, are the same bit
+    for bit whatever the K segment length, the lane count and the operand
+    overlap.  The segment length is set through the autotuner's cache: one
+    tuning run writes the plan's entry, which is then rewritten to each
+    candidate length and read back."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=16384)   # K segments of 4096 (the default), 8192, 16384
+    insts = [dict(lam=LAM0, M=128), dict(lam=600e-9, M=64, x0=2e-6)]
+    cache = tmp_path / "tune.txt"
+    ref = None
+    for kw in (dict(), dict(overlap_operand=True), dict(lanes=2)):
+        plan = P.Plan(ap, insts, path="split", int8=True, chunk_rows=1024, allow_undersampled=True, **kw)
+        ws, roi = plan.alloc()
+        plan.propagate(ws, roi)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = roi.clone()
+            tune = plan.autotune(ws, roi, str(cache))
+            announce(f"autotune {tune}")
+            assert tune["variant"] % 8 == 4       # the int8 row pass has one form; the BF16 default stays
+            key, _, ln, tl = cache.read_text().split("\n")[0].split()
+            assert key.endswith("/128f/64f") and "/i8" in key
+            for seg in (4096, 8192, 16384):
+                cache.write_text(f"{key} {seg} {ln} {tl}\n")
+                got = plan.autotune(ws, roi, str(cache))
+                assert got["seg_len"] == seg
+                plan.propagate(ws, roi)
+                torch.cuda.synchronize()
+                announce(f"K segments of {seg}: bit-identical {torch.equal(roi, ref)}")
+                assert torch.equal(roi, ref), seg
+        else:
+            announce(f"schedule {kw}: bit-identical {torch.equal(roi, ref)}")
+            assert torch.equal(roi, ref), kw
+        del ws, roi, plan
