@@ -1,14 +1,16 @@
-// Row pass on the int8 matrix cores for binary stripes (FZP_FLAG_SPLIT_INT8).
+// Row pass on the int8 matrix cores (FZP_FLAG_SPLIT_INT8).
 //
-// Same product as the split-BF16 row pass (Sec. 2.6: the binary zone mask of
-// Eq. 4, generated on the fly, times the N x M kernel matrix
+// Same product as the split-BF16 row pass (Sec. 2.6: the stripe of Eq. 4
+// zones, generated on the fly, times the N x M kernel matrix
 //   A[i][q] = exp(2 pi i (beta c_i^2/2 - alpha c_i d_q))),
 // with A held in fixed point instead of a BF16 hi/lo pair: v = rint(A s),
 // s = kI8Scale = 16256, split into two balanced int8 digits v = 128 v0 + v1.
-// The mask is 0 / 1 in int8, so both digit products sum exactly in int32 and
-// the only error is the quantisation of A (at most 0.5 / 16256 = 3.1e-5 per
-// component).  Per 32 columns of K the int8 MFMA does the work of two BF16
-// MFMA K-steps, so the two digits cost what one BF16 plane does.
+// Binary stripes: the mask is 0 / 1 in int8, so both digit products sum
+// exactly in int32 and the only error is the quantisation of A (at most
+// 0.5 / 16256 = 3.1e-5 per component); per 32 columns of K the int8 MFMA does
+// the work of two BF16 MFMA K-steps, so the two digits cost what one BF16
+// plane does.  Complex stripes (creases, L-level plates) hold the stripe in
+// digits too (k_row_pass_i8_cplx below).
 //
 // Table layout, blocked by 64 aperture columns (one 64-byte row per column and
 // block, as the BF16 table's 32-column blocks):
@@ -54,22 +56,6 @@ __global__ __launch_bounds__(256) void k_build_i8_table(InstDev d, int8_t *__res
 
 constexpr int kTC = 128;  // real columns per tile (64 complex ROI columns), as the BF16 row pass
 
-// ---------------------------------------------------------------------------
-// The row-pass kernel: T = (128 (mask . v0) + mask . v1), in int32 (the
-// column pass scales it by 1 / 16256); |T| <= 65536 (127 * 128 + 64) < 2^31
-// for K segments up to 65536 columns.  One v_mfma_i32_32x32x32_i8 covers 32
-// columns of K.
-//
-// Same work-group tile (512 rows x 128 real columns), wave layout (4 x 2 waves
-// of 4 x 2 MFMA blocks), XCD-aware order, K trimming to the disc chord and
-// direct global -> LDS ring as the BF16 binary row pass; a stage is 64
-// columns of K (two MFMA K-steps: a 64-byte table row per ROI column, two mask
-// words per row).  The two digit planes are swept one after the other over the
-// K segment (the accumulators of both would not fit beside the operands):
-// digit 0, the accumulators times 128, then digit 1.  Partial sums are stored
-// as int32 bits in the float32 partial planes; the column pass converts them
-// (k_col_operand).
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Zone-mask bits for the int8 row pass.  The same bits as k_mask_bits (Sec.
 // 2.2, Eq. 4: zone = floor(K kappa) from the exact integer K, the disc chord,
@@ -464,10 +450,11 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
   if (k_hi > 16 * (kb0 + nkb)) k_hi = 16 * (kb0 + nkb);
 
   // ---- copy roles.  Stripe: wave w copies pieces x = 4w .. 4w+3 (plane x / 8,
-  // rows 32 (x % 8) ..); table: piece w (plane w / 4, columns 32 (w % 4) ..).  Lane L fills LDS row L / 2, half L & 1, which holds the
-  // global half chalf8(row, L & 1): stripe block k / 16 + half, table bytes
-  // k % 64 + 16 half.  Table columns past 2M read column 0: they feed only
-  // accumulator columns that are never stored.
+  // rows 32 (x % 8) ..); table: piece w (plane w / 4, columns 32 (w % 4) ..).
+  // Lane L fills LDS row L / 2, half L & 1, which holds the global half
+  // chalf8(row, L & 1): stripe block k / 16 + half, table bytes k % 64 +
+  // 16 half.  Table columns past 2M read column 0: they feed only accumulator
+  // columns that are never stored.
   const int64_t gplane = nkb * rows_pad * 16;     // bytes per stripe plane
   const int64_t tplane = (int64_t)M2 * d.Npad;    // bytes per table plane
   const int8_t *gsrc[4];
