@@ -73,7 +73,12 @@ typedef int32_t fzp_status_t;
                                      largest M is at most 1024 (binary plate, or crease-free
                                      2-level phase plate), 256 (creased amplitude plate, or
                                      crease-free 4-level phase plate), 128 (other phase
-                                     plates); fzp_plan_info reports the choice */
+                                     plates); twice these with FZP_FLAG_SPLIT_INT8, whose row
+                                     pass takes half the matrix-core time (measured faster than
+                                     the FP64 path at binary M = 1024, creased M of 256 .. 1024
+                                     (mean ~600) and 4-level M = 512), the flag being dropped
+                                     when the FP64 path is chosen; fzp_plan_info reports the
+                                     choice */
 #define FZP_PATH_SA_CZT 3         /* non-paraxial variant, the semi-analytical chirp-z transform
                                      (Sec. 3.6, Fig. 5): the amplitude plate with the sag-corrected
                                      radii of Eq. 3 centred in a zero-padded grid of Np >= 1.5 N
@@ -115,7 +120,7 @@ typedef int32_t fzp_status_t;
                                          matrix-core work; quantisation error <= 3.1e-5 per element
                                          (the BF16 pair rounds to ~4e-6), and for complex stripes
                                          the digit-1 x digit-1 product (<= 1.5e-5) left out;
-                                         FZP_E_UNSUPPORTED on another path */
+                                         FZP_E_UNSUPPORTED on the FP64 or SA-CZT path */
 #define FZP_FLAG_OVERLAP_OPERAND 16   /* split path: make each chunk's stripe operand on an internal
                                          auxiliary stream one chunk ahead of its GEMM (two operand
                                          buffers); not under stream capture: fzp_graph_create,

@@ -225,7 +225,10 @@ extern "C" fzp_status_t fzp_plan(const fzp_aperture_t *ap, const fzp_instance_t 
       int limit = 128;
       if ((ap->levels == 0 || ap->levels == 2) && !creased) limit = 1024;  // binary GEMM
       else if (ap->levels == 0 || (ap->levels == 4 && !creased)) limit = 256;  // two binary GEMMs, or complex
+      // the int8 row pass takes half the matrix-core time of the BF16 one
+      if (o.flags & FZP_FLAG_SPLIT_INT8) limit *= 2;
       o.path = m16 && mmax <= limit ? FZP_PATH_SPLIT_BF16 : FZP_PATH_FP64_BLUESTEIN;
+      if (o.path != FZP_PATH_SPLIT_BF16) o.flags &= ~FZP_FLAG_SPLIT_INT8;  // a form of the split path only
     }
     if (!finite_pos(ap->D) || !finite_pos(ap->f0) || !finite_pos(ap->lambda0))
       return fail(FZP_E_INVAL, "fzp_plan: D, f0 and lambda0 must be finite and positive");

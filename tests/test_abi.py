@@ -319,3 +319,16 @@ def test_split_int8_plan_validation():
         with pytest.raises(P.FZPError) as e:
             P.Plan(base, [dict(lam=LAM0, M=64)], path=path, int8=True)
         assert e.value.status == P.FZP_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("levels,creased,M,want", [
+    (0, False, 2048, L.PATH_SPLIT_BF16), (0, True, 512, L.PATH_SPLIT_BF16), (0, True, 1024, L.PATH_FP64_BLUESTEIN),
+    (4, False, 512, L.PATH_SPLIT_BF16), (8, False, 256, L.PATH_SPLIT_BF16), (8, False, 512, L.PATH_FP64_BLUESTEIN)])
+def test_auto_path_with_int8_doubles_the_crossover(levels, creased, M, want):
+    """With FZP_FLAG_SPLIT_INT8 the auto path takes the split path up to twice
+    the BF16 crossovers (half the matrix-core time); when it picks the FP64
+    path the flag is dropped instead of refused."""
+    cr = [[0.3, 0.0, 2e-4, 1e-7]] if creased else None
+    plan = P.Plan(dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048, levels=levels),
+                  [dict(lam=LAM0, M=M, creases=cr)], path="auto", int8=True)
+    assert plan.info()["path"] == want
