@@ -631,7 +631,7 @@ def main():
         row8 = pr8["row_ms"] / max(args.steps, 1)
         ops = 8.0 * M * float(r["info"]["disc_samples"])
         ach8 = ops / (row8 * 1e-3) / 1e12
-        res = {"gsamples_s": round(samples / (r["ms"] * 1e-3) / 1e9, 3), "ms_per_step": round(r["ms"], 3),
+        res = {"dtype": "i8", "gsamples_s": round(samples / (r["ms"] * 1e-3) / 1e9, 3), "ms_per_step": round(r["ms"], 3),
                "row_pass_ms": round(row8, 3), "mask_bits_ms": round(pr8["mask_ms"] / max(args.steps, 1), 3),
                "col_pass_ms": round(pr8["col_ms"] / max(args.steps, 1), 3), "metrics": r["metrics"],
                "roofline": dict(bound="mfma", achieved=round(ach8, 1), peak=PEAK_INT8_TOPS, unit="TOP/s",
