@@ -189,13 +189,16 @@ __global__ __launch_bounds__(kCTR) void k_stripe_cplx(InstDev d, int64_t row_beg
       uint32_t w8[4][4] = {};
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        float sn, cs;
-        sincos_turns(turns[e], sn, cs);
+        // sin and cos of 2 pi t from the hardware's transcendental unit, whose
+        // input is in turns (valid to +-256; here |t| is a few turns): its
+        // error is far below the digits' quantisation step of 1 / 16256
+        const float sn = __builtin_amdgcn_sinf(turns[e]), cs = __builtin_amdgcn_cosf(turns[e]);
         const bool o = (open >> e) & 1u;
         const int vr = o ? (int)rintf(cs * (float)kI8Scale) : 0, vi = o ? (int)rintf(sn * (float)kI8Scale) : 0;
-        const int lr = ((vr + 64) & 127) - 64, li = ((vi + 64) & 127) - 64;
-        const uint32_t dg[4] = {(uint32_t)(((vr - lr) >> 7) & 0xff), (uint32_t)(lr & 0xff),
-                                (uint32_t)(((vi - li) >> 7) & 0xff), (uint32_t)(li & 0xff)};
+        // balanced digits v = 128 d0 + d1, d1 in [-64, 63]
+        const int r0 = (vr + 64) >> 7, i0 = (vi + 64) >> 7;
+        const uint32_t dg[4] = {(uint32_t)(r0 & 0xff), (uint32_t)((vr - (r0 << 7)) & 0xff), (uint32_t)(i0 & 0xff),
+                                (uint32_t)((vi - (i0 << 7)) & 0xff)};
 #pragma unroll
         for (int v = 0; v < 4; ++v) w8[v][e >> 2] |= dg[v] << (8 * (e & 3));
       }
