@@ -110,46 +110,38 @@ __global__ __launch_bounds__(256) void k_mask_bits_i8(InstDev d, int64_t row_beg
     uint32_t v[4], v2[4], vm[4], vm2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      // each bit goes straight to its permuted place, and for the mirrored
-      // word to the place of its bit-reversed position; the chord mask is
+      // each bit goes straight to its permuted place; the chord mask is
       // permuted the same way (perm_i8 distributes over and / xor, and the
-      // centre-open flip is all ones or zero)
+      // centre-open flip is all ones or zero).  The mirrored word is the
+      // bit-reversed natural word, and bit reversal commutes with the
+      // permutation (reversing a 5-bit index complements each of its fields,
+      // which maps position p to 31 - p), so it is the permuted word reversed.
       const int64_t i0 = 32 * (int64_t)(4 * g + q);
       v[q] = v2[q] = vm[q] = vm2[q] = 0;
       if (i0 < rhi && i0 + 32 > rlo) {
         double ci = (double)(2 * i0 - Nm1);
-        uint32_t a = 0, a2 = 0, am = 0, am2 = 0;
+        uint32_t a = 0, a2 = 0;
 #pragma unroll
         for (int e = 0; e < 32; ++e) {
           const int pe = 8 * (e & 3) + 4 * (e >> 4) + ((e >> 2) & 3);
-          const int f = 31 - e, pf = 8 * (f & 3) + 4 * (f >> 4) + ((f >> 2) & 3);
           const double K = fma(ci, ci, bj);
           if constexpr (FOUR) {
             const int z = (int)(K * d.kappa_l);
-            const uint32_t b1 = (uint32_t)(z >> 1) & 1u, b2 = (uint32_t)(z ^ (z >> 1)) & 1u;
-            a |= b1 << pe;
-            a2 |= b2 << pe;
-            am |= b1 << pf;
-            am2 |= b2 << pf;
+            a |= ((uint32_t)(z >> 1) & 1u) << pe;
+            a2 |= ((uint32_t)(z ^ (z >> 1)) & 1u) << pe;
           } else {
-            const uint32_t b1 = (uint32_t)(int)(K * d.kappa) & 1u;
-            a |= b1 << pe;
-            am |= b1 << pf;
+            a |= ((uint32_t)(int)(K * d.kappa) & 1u) << pe;
           }
           ci += 2.0;
         }
         const int lo = (int)min(max(rlo - i0, (int64_t)0), (int64_t)32);
         const int hi = (int)min(max(rhi - i0, (int64_t)0), (int64_t)32);
         const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-        uint32_t pv = 0xffffffffu, pvm = 0xffffffffu;
-        if (valid != 0xffffffffu) {
-          pv = perm_i8(valid);
-          pvm = perm_i8(__builtin_bitreverse32(valid));
-        }
+        const uint32_t pv = valid != 0xffffffffu ? perm_i8(valid) : 0xffffffffu;
         v[q] = (a ^ flip) & pv;
-        vm[q] = (am ^ flip) & pvm;
         v2[q] = a2 & pv;
-        vm2[q] = am2 & pvm;
+        vm[q] = __builtin_bitreverse32(v[q]);
+        vm2[q] = __builtin_bitreverse32(v2[q]);
       }
     }
     uint4 *o = (uint4 *)bits + (int64_t)g * rows_pad + rl;
