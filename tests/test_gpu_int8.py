@@ -198,3 +198,48 @@ def test_int8_binary_sums_do_not_depend_on_the_schedule(tmp_path):
             announce(f"schedule {kw}: bit-identical {torch.equal(roi, ref)}")
             assert torch.equal(roi, ref), kw
         del ws, roi, plan
+
+
+LIMITS = {
+    "roi_m16": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048), dict(lam=LAM0, M=16)),
+    "roi_m2048": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048), dict(lam=LAM0, M=2048)),
+    "n100": (dict(D=1e-3, f0=10e-3, lambda0=LAM0, N=100), dict(lam=LAM0, M=32)),
+    "n100_creased": (dict(D=1e-3, f0=10e-3, lambda0=LAM0, N=100),
+                     dict(lam=LAM0, M=32, creases=crease_draws(3, 1e-3, LAM0, 4) * np.array([1, 1, 0.3, 1]))),
+    "creased_m1024": (dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=2048),
+                      dict(lam=600e-9, M=1024, creases=crease_draws(4, 2e-3, LAM0, 8) * np.array([1, 1, 0.2, 1]))),
+}
+
+
+@pytest.mark.parametrize("case", list(LIMITS))
+def test_int8_limits(case):
+    """The smallest and largest ROIs, an aperture smaller than one row tile and
+    one K stage (binary and creased), and a large creased ROI (16 column
+    tiles), against the oracle."""
+    ap, inst = LIMITS[case]
+    announce(f"limits {case}: N={ap['N']} M={inst['M']}")
+    _, _, _, U = run(ap, inst, path="split", int8=True, allow_undersampled=True)
+    ref = O.propagate(*oracle(ap, inst), stripe=64 if ap["N"] < 512 else 512)
+    e, ei = rel_l2(U, ref), rel_l2(O.intensity(U), O.intensity(ref))
+    announce(f"  complex {e:.2e} intensity {ei:.2e}")
+    assert e <= 1e-4 and ei <= 1e-4
+
+
+def test_int8_largest_aperture_sampled_stripe():
+    """N = 2^21 (the split path's largest grid in one segment schedule): a 2 m
+    f/5 plate at 0.95 um pitch, 64 rows through the centre against the
+    oracle's restricted row sum."""
+    N = 1 << 21
+    ap = dict(D=2.0, f0=10.0, lambda0=LAM0, N=N)
+    inst = dict(lam=LAM0, M=512)
+    plan = P.Plan(ap, [inst], path="split", int8=True, stripe_rows=64)
+    ws, roi = plan.alloc()
+    j0 = N // 2 - 32
+    announce(f"N=2^21 int8 stripe rows {j0}..{j0 + 64}")
+    plan.propagate_range(ws, roi, j0, j0 + 64, accumulate=False)
+    torch.cuda.synchronize()
+    U = plan.roi_view(roi, 0).cpu().numpy()
+    ref = O.propagate(*oracle(ap, inst), method="bluestein", rows=(j0, j0 + 64), stripe=16)
+    e = rel_l2(U, ref)
+    announce(f"  complex rel-L2 {e:.3e}")
+    assert e <= 1e-4
