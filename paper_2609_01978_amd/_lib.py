@@ -221,7 +221,11 @@ def _ptr(t) -> int:
 
 
 class Plan:
-    """A propagation plan: an aperture and one or more instances (lambda, z, ROI, creases)."""
+    """A propagation plan: an aperture and one or more instances (lambda, z, ROI, creases).
+
+    path: "fp64", "split", "auto" or "sa"; int8=True selects the split path's
+    int8 row pass (FZP_FLAG_SPLIT_INT8); the other keywords map to
+    fzp_options_t fields and FZP_FLAG_* bits as named."""
 
     def __init__(self, aperture: dict, instances: Sequence[dict], path: str = "fp64", stripe_rows: int = 0,
                  chunk_rows: int = 0, workspace_limit: int = 0, allow_undersampled: bool = False,
