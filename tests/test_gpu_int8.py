@@ -243,3 +243,19 @@ def test_int8_largest_aperture_sampled_stripe():
     e = rel_l2(U, ref)
     announce(f"  complex rel-L2 {e:.3e}")
     assert e <= 1e-4
+
+
+def test_int8_tall_ridge_phase_reduction():
+    """A ridge far wider than the pupil and 300.37 wavelengths tall adds a
+    near-uniform phase of about 300 turns, beyond the transcendental unit's
+    +-256-turn input range unless the stripe generator reduces the turns
+    first: the intensity must still be the oracle's (a uniform phase is
+    invisible in it), on both split forms."""
+    ap = dict(D=2e-3, f0=10e-3, lambda0=LAM0, N=1536)
+    inst = dict(lam=LAM0, M=96, creases=np.array([[0.3, 0.0, 1e6, 300.37 * LAM0]]))
+    ref = O.intensity(O.propagate(*oracle(ap, inst), stripe=512))
+    for int8 in (True, False):
+        _, _, _, U = run(ap, inst, path="split", int8=int8, allow_undersampled=True)
+        e = rel_l2(O.intensity(U), ref)
+        announce(f"tall ridge int8={int8}: intensity rel-L2 {e:.2e}")
+        assert e <= 1e-4
