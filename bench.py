@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--sa-steps", type=int, default=3)
     ap.add_argument("--no-int8", action="store_true",
                     help="skip the int8 row pass (FZP_FLAG_SPLIT_INT8) on the same workload")
-    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate", "int8"],
+    ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate", "int8",
+                                       "batch_int8_one_lane"],
                     default=None,
                     help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -262,6 +263,25 @@ def run_batch(args, dev):
             "split_bf16": res["split"], "fp64_bluestein": res["fp64"], "split_int8": res["split_int8"],
             "max_rel_l2_split_vs_fp64": max(errs), "valid_rel_l2_le_1e-4": max(errs) <= 1e-4,
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_batch"] / res["split"]["ms_per_batch"], 3)}
+
+
+def run_batch_int8_one_lane(dev):
+    """One propagation of the creased batch on the int8 row pass, one lane,
+    default K segments: the configuration of the batch roofline, alone, for
+    counter runs of its kernels."""
+    import torch
+    import paper_2609_01978_amd as P
+    from fzp_inputs import workload, batch64_instances
+    w = workload("batch64")
+    ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
+    insts = batch64_instances()
+    plan = P.Plan(ap, insts, path="split", lanes=1, int8=True)
+    ws, roi = plan.alloc(dev)
+    t0 = time.perf_counter()
+    plan.propagate(ws, roi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"instances": len(insts), "ms_first_propagation": round(dt * 1e3, 3)}
 
 
 def run_multilevel(args, dev, levels=None):
@@ -579,7 +599,8 @@ def main():
         torch.cuda.set_device(dev)
         run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
                "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev),
-               "blas": lambda: run_blas(dev), "surrogate": lambda: run_surrogate(args)}[args.only]
+               "blas": lambda: run_blas(dev), "surrogate": lambda: run_surrogate(args),
+               "batch_int8_one_lane": lambda: run_batch_int8_one_lane(dev)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
