@@ -243,8 +243,13 @@ def run_batch(args, dev):
         flops = sum(24.0 * inst["M"] * disc for inst in insts)
         ach = flops / (pr["row_ms"] * 1e-3) / 1e12
         peak = PEAK_INT8_TOPS if i8 else PEAK_BF16_TFLOPS
+        summary = "profiles/counters_k_row_pass_i8_cplx_batch64.md"
         res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=peak,
                                      unit="TOP/s" if i8 else "TFLOP/s", frac=round(ach / peak, 4),
+                                     traffic=committed_traffic(I8_SOURCES, summary) if i8 else None,
+                                     mfma_busy=committed_value(I8_SOURCES, summary, "mfma_busy_fraction_of_cycles")
+                                     if i8 else None,
+                                     committed_from=summary + " (traffic per launch, mfma_busy)" if i8 else None,
                                      kernel="k_row_pass_i8_cplx" if i8 else "k_row_pass_split_cplx",
                                      launches=pr["row_launches"], row_gemm_ms=round(pr["row_ms"], 3),
                                      stripe_ms=round(pr["mask_ms"], 3), col_pass_ms=round(pr["col_ms"], 3),
