@@ -76,9 +76,9 @@ typedef int32_t fzp_status_t;
                                      plates); twice these with FZP_FLAG_SPLIT_INT8, whose row
                                      pass takes half the matrix-core time (measured faster than
                                      the FP64 path at binary M = 1024, creased M of 256 .. 1024
-                                     (mean ~600) and 4-level M = 512), the flag being dropped
-                                     when the FP64 path is chosen; fzp_plan_info reports the
-                                     choice */
+                                     (mean ~600), 4-level M = 512 and 8- and 16-level M = 256,
+                                     slower at 8-level M = 512), the flag being dropped when the
+                                     FP64 path is chosen; fzp_plan_info reports the choice */
 #define FZP_PATH_SA_CZT 3         /* non-paraxial variant, the semi-analytical chirp-z transform
                                      (Sec. 3.6, Fig. 5): the amplitude plate with the sag-corrected
                                      radii of Eq. 3 centred in a zero-padded grid of Np >= 1.5 N
