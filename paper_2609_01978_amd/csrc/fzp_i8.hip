@@ -394,15 +394,19 @@ constexpr int kCWait8 = 5;
 __device__ __forceinline__ int chalf8(int row, int half) { return half ^ ((row >> 3) & 1); }
 
 // Column n's B operand from lane l ^ 1 (column n ^ 1, the same K half), each
-// byte negated on even columns: -b = ((0x80 - (b & 0x7f)) ^ 0x80) ^ (b & 0x80)
-// per byte, with no carry between bytes.
-__device__ __forceinline__ i32x4 swap_neg_i8(i32x4 b, bool even) {
+// byte negated on even columns.  For a byte b other than -128 (digits lie in
+// [-127, 127]), -b = ((b ^ 0x7f) + 1) ^ 0x80 with no carry out of the byte
+// (b ^ 0x7f keeps the sign bit and takes the low seven bits to 0x7f - l, and
+// adding one carries into bit 7 only for l = 0, where b = 0 gives 0x80 and
+// the final flip 0).  The lane's constants are zero on odd columns, where
+// the expression is the identity: k7 = 0x7f7f7f7f, k1 = 0x01010101,
+// k8 = 0x80808080 on even lanes.
+__device__ __forceinline__ i32x4 swap_neg_i8(i32x4 b, uint32_t k7, uint32_t k1, uint32_t k8) {
   i32x4 r;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t u = (uint32_t)__builtin_amdgcn_mov_dpp(b[j], 0xb1, 0xf, 0xf, true);  // quad_perm [1,0,3,2]
-    const uint32_t n = ((0x80808080u - (u & 0x7f7f7f7fu)) ^ 0x80808080u) ^ (u & 0x80808080u);
-    r[j] = (int32_t)(even ? n : u);
+    r[j] = (int32_t)(((u ^ k7) + k1) ^ k8);
   }
   return r;
 }
@@ -471,6 +475,7 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
   const int aoff = (wr * 64 + l32) * kCRowB8 + hofs;
   const int boff = kCG8 + (wc * 64 + l32) * kCRowB8 + hofs;
   const bool even = (lane & 1) == 0;
+  const uint32_t k7 = even ? 0x7f7f7f7fu : 0u, k1 = even ? 0x01010101u : 0u, k8 = even ? 0x80808080u : 0u;
 
   i32x16 ah[2][2], ax[2][2];
 #pragma unroll
@@ -509,8 +514,8 @@ __global__ __launch_bounds__(512, 1) void k_row_pass_i8_cplx(InstDev d, int64_t 
 #pragma unroll
         for (int t = 0; t < 2; ++t)
           b[cb][t] = __builtin_bit_cast(i32x4, lds_ld16(sb + boff + t * kCTC8 * kCRowB8 + cb * 32 * kCRowB8));
-        b[cb][2] = swap_neg_i8(b[cb][0], even);
-        b[cb][3] = swap_neg_i8(b[cb][1], even);
+        b[cb][2] = swap_neg_i8(b[cb][0], k7, k1, k8);
+        b[cb][3] = swap_neg_i8(b[cb][1], k7, k1, k8);
       }
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
