@@ -54,7 +54,7 @@ constexpr int kCRowB = 32;    // LDS bytes per slab row
 constexpr int kCGBytes = 4 * kCTR * kCRowB;   // 32768: four stripe planes
 constexpr int kCBBytes = 2 * kCTC * kCRowB;   // 16384: table hi and lo
 constexpr int kCStage = kCGBytes + kCBBytes;  // 49152
-constexpr int kCRing = 3, kCAhead = 2;
+constexpr int kCRing = 3;  // LDS stages (the default tile); copies run kCRing - 1 stages ahead
 constexpr int kCLdsBytes = kCRing * kCStage;  // 147456
 // LDS of a tile with CT real columns and a ring of RING stages
 constexpr int cplx_lds_bytes(int CT, int RING = kCRing) { return RING * (kCGBytes + 2 * CT * kCRowB); }
