@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--no-int8", action="store_true",
                     help="skip the int8 row pass (FZP_FLAG_SPLIT_INT8) on the same workload")
     ap.add_argument("--only", choices=["batch", "ml100mm", "sa", "configs", "blas", "surrogate", "int8",
-                                       "batch_int8_one_lane"],
+                                       "batch_split_one_lane", "batch_int8_one_lane"],
                     default=None,
                     help="run only this section (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -79,10 +79,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# sources of the dominant kernel (k_row_pass_split); its committed HBM counters
-# are reported only while these are unchanged
+# sources of the row GEMMs whose committed counters (profiles/) the bench
+# reports: the binary BF16 kernel (the dominant one), the int8 kernels and the
+# complex BF16 kernel; each figure is reported only while its sources are unchanged
 GEMM_SOURCES = ["paper_2609_01978_amd/csrc/fzp_gemm.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
 I8_SOURCES = ["paper_2609_01978_amd/csrc/fzp_i8.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
+CPLX_SOURCES = ["paper_2609_01978_amd/csrc/fzp_cplx.hip", "paper_2609_01978_amd/csrc/fzp_split.h"]
 
 # MI355X published peaks
 PEAK_BF16_TFLOPS = 2500.0
@@ -243,13 +245,18 @@ def run_batch(args, dev):
         flops = sum(24.0 * inst["M"] * disc for inst in insts)
         ach = flops / (pr["row_ms"] * 1e-3) / 1e12
         peak = PEAK_INT8_TOPS if i8 else PEAK_BF16_TFLOPS
-        summary = "profiles/counters_k_row_pass_i8_cplx_batch64.md"
+        # counters of this configuration's row GEMM, taken in runs of their own
+        # (bench.py --only batch_split_one_lane / batch_int8_one_lane)
+        summary = ("profiles/counters_k_row_pass_i8_cplx_batch64.md" if i8
+                   else "profiles/counters_k_row_pass_split_cplx_batch64.md")
+        srcs = I8_SOURCES if i8 else CPLX_SOURCES
+        traffic = committed_traffic(srcs, summary)
+        busy = committed_value(srcs, summary, "mfma_busy_fraction_of_cycles")
         res[path]["roofline"] = dict(bound="mfma", achieved=round(ach, 1), peak=peak,
                                      unit="TOP/s" if i8 else "TFLOP/s", frac=round(ach / peak, 4),
-                                     traffic=committed_traffic(I8_SOURCES, summary) if i8 else None,
-                                     mfma_busy=committed_value(I8_SOURCES, summary, "mfma_busy_fraction_of_cycles")
-                                     if i8 else None,
-                                     committed_from=summary + " (traffic per launch, mfma_busy)" if i8 else None,
+                                     traffic=traffic, mfma_busy=busy,
+                                     committed_from=summary + " (traffic per launch, mfma_busy)"
+                                     if traffic is not None or busy is not None else None,
                                      kernel="k_row_pass_i8_cplx" if i8 else "k_row_pass_split_cplx",
                                      launches=pr["row_launches"], row_gemm_ms=round(pr["row_ms"], 3),
                                      stripe_ms=round(pr["mask_ms"], 3), col_pass_ms=round(pr["col_ms"], 3),
@@ -270,17 +277,17 @@ def run_batch(args, dev):
             "speedup_split_vs_fp64": round(res["fp64"]["ms_per_batch"] / res["split"]["ms_per_batch"], 3)}
 
 
-def run_batch_int8_one_lane(dev):
-    """One propagation of the creased batch on the int8 row pass, one lane,
-    default K segments: the configuration of the batch roofline, alone, for
-    counter runs of its kernels."""
+def run_batch_one_lane(dev, int8: bool):
+    """One propagation of the creased batch on the split path (int8 or BF16
+    row pass), one lane, default K segments and tile: the configuration of the
+    batch roofline, alone, for counter runs of its kernels."""
     import torch
     import paper_2609_01978_amd as P
     from fzp_inputs import workload, batch64_instances
     w = workload("batch64")
     ap = dict(D=w["D"], f0=w["f0"], lambda0=w["lambda0"], N=w["N"])
     insts = batch64_instances()
-    plan = P.Plan(ap, insts, path="split", lanes=1, int8=True)
+    plan = P.Plan(ap, insts, path="split", lanes=1, int8=int8)
     ws, roi = plan.alloc(dev)
     t0 = time.perf_counter()
     plan.propagate(ws, roi)
@@ -605,7 +612,8 @@ def main():
         run = {"batch": lambda: run_batch(args, dev), "ml100mm": lambda: run_multilevel(args, dev),
                "sa": lambda: run_sa(args, dev), "configs": lambda: run_configs(dev),
                "blas": lambda: run_blas(dev), "surrogate": lambda: run_surrogate(args),
-               "batch_int8_one_lane": lambda: run_batch_int8_one_lane(dev)}[args.only]
+               "batch_split_one_lane": lambda: run_batch_one_lane(dev, int8=False),
+               "batch_int8_one_lane": lambda: run_batch_one_lane(dev, int8=True)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
