@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_mask_bits_i8(InstDev d, int64_t row_beg
     uint32_t v[4], v2[4], vm[4], vm2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      // each bit goes straight to its permuted place; the chord mask is
+      // each bit is gathered into its permuted place; the chord mask is
       // permuted the same way (perm_i8 distributes over and / xor, and the
       // centre-open flip is all ones or zero).  The mirrored word is the
       // bit-reversed natural word, and bit reversal commutes with the
@@ -120,20 +120,27 @@ __global__ __launch_bounds__(256) void k_mask_bits_i8(InstDev d, int64_t row_beg
       v[q] = v2[q] = vm[q] = vm2[q] = 0;
       if (i0 < rhi && i0 + 32 > rlo) {
         double ci = (double)(2 * i0 - Nm1);
-        uint32_t a = 0, a2 = 0;
+        // Column e goes to bit 8 (e & 3) + (e >> 2) of the permuted word: inside
+        // byte lane e & 3 the bit position rises with e, so each lane collects
+        // its 8 bits by a funnel shift from the top (one instruction per
+        // sample) and ends with them in bits 24..31.
+        uint32_t acc[4] = {0u, 0u, 0u, 0u}, acc2[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int e = 0; e < 32; ++e) {
-          const int pe = 8 * (e & 3) + 4 * (e >> 4) + ((e >> 2) & 3);
           const double K = fma(ci, ci, bj);
           if constexpr (FOUR) {
             const int z = (int)(K * d.kappa_l);
-            a |= ((uint32_t)(z >> 1) & 1u) << pe;
-            a2 |= ((uint32_t)(z ^ (z >> 1)) & 1u) << pe;
+            acc[e & 3] = __builtin_amdgcn_alignbit((uint32_t)(z >> 1), acc[e & 3], 1);
+            acc2[e & 3] = __builtin_amdgcn_alignbit((uint32_t)(z ^ (z >> 1)), acc2[e & 3], 1);
           } else {
-            a |= ((uint32_t)(int)(K * d.kappa) & 1u) << pe;
+            acc[e & 3] = __builtin_amdgcn_alignbit((uint32_t)(int)(K * d.kappa), acc[e & 3], 1);
           }
           ci += 2.0;
         }
+        const uint32_t a = (acc[0] >> 24) | ((acc[1] >> 16) & 0xff00u) | ((acc[2] >> 8) & 0xff0000u) |
+                           (acc[3] & 0xff000000u);
+        const uint32_t a2 = (acc2[0] >> 24) | ((acc2[1] >> 16) & 0xff00u) | ((acc2[2] >> 8) & 0xff0000u) |
+                            (acc2[3] & 0xff000000u);
         const int lo = (int)min(max(rlo - i0, (int64_t)0), (int64_t)32);
         const int hi = (int)min(max(rhi - i0, (int64_t)0), (int64_t)32);
         const uint32_t valid = (hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
